@@ -1,0 +1,286 @@
+"""Truncated Neumann series S_k(A) by low-product radix kernels on MI355X.
+
+Thin ctypes binding over ``libns.so`` (C ABI in ``include/ns.h``).  Every
+step of the computation runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory and streams: tensors are
+passed by ``data_ptr()`` and the current stream.  Importing this module fails
+loudly if the library has not been built (``python -m
+paper_2602_11843_amd.build``); there is no CPU fallback.
+"""
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libns.so")
+
+# methods (enum ns_method)
+NAIVE, BINARY, RADIX9, RADIX15, RADIX9_RESID, QUINARY, TERNARY, HENSEL = range(8)
+METHODS = {"naive": NAIVE, "binary": BINARY, "radix9": RADIX9, "radix15": RADIX15,
+           "radix9_resid": RADIX9_RESID, "quinary": QUINARY, "ternary": TERNARY,
+           "hensel": HENSEL}
+# compute precision (enum ns_dtype)
+F64, F32, SPLIT_BF16, F16_SCALED, F32_ACC64 = range(5)
+DTYPES = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16, "f16_scaled": F16_SCALED,
+          "f32_acc64": F32_ACC64}
+
+MAX_LEVELS = 64
+
+
+class NSError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("k_eff", ctypes.c_int64),
+        ("levels", ctypes.c_int32),
+        ("gemms_performed", ctypes.c_int32),
+        ("gemms_formula", ctypes.c_int32),
+        ("nonfinite", ctypes.c_int32),
+        ("n_internal", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("level_norm", ctypes.c_double * MAX_LEVELS),
+        ("kernel_prefix_err", ctypes.c_double),
+        ("spill15", ctypes.c_double),
+        ("spill16", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {
+            "k_eff": self.k_eff, "levels": self.levels,
+            "gemms_performed": self.gemms_performed, "gemms_formula": self.gemms_formula,
+            "nonfinite": bool(self.nonfinite), "n_internal": self.n_internal,
+            "level_norm": [self.level_norm[i] for i in range(min(self.levels, MAX_LEVELS))]
+            if self.method != NAIVE else [],
+            "kernel_prefix_err": self.kernel_prefix_err,
+            "spill15": self.spill15, "spill16": self.spill16,
+        }
+
+
+# exported symbols and their signatures: (restype, argtypes)
+_P, _I64, _I32, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+_SIGNATURES = {
+    "ns_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int]),
+    "ns_destroy": (ctypes.c_int, [_P]),
+    "ns_plan": (ctypes.c_int, [_I64, ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                               ctypes.POINTER(_I32)]),
+    "ns_workspace_bytes": (ctypes.c_int, [_I64, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "ns_eval": (ctypes.c_int, [_P, _I64, _I64, ctypes.c_int, ctypes.c_int, _P]),
+    "ns_eval_ex": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _P, _I64,
+                                  _P, ctypes.POINTER(Report)]),
+    "ns_eval_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I64, ctypes.c_int, ctypes.c_int,
+                                       _P, _P, ctypes.POINTER(Report)]),
+    "ns_eval_batched_loop": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, ctypes.c_int,
+                                            ctypes.c_int, _P, _P]),
+    "ns_autotune_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I64, _P, _P,
+                                           ctypes.POINTER(_I32)]),
+    "ns_radix15_coeffs": (ctypes.c_int, [ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                         ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "ns_set_product_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ns_product_timing": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_D),
+                                         ctypes.POINTER(_D), ctypes.c_int]),
+    "ns_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ns_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2602_11843_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise NSError(status, where, lib.ns_last_error().decode(errors="replace"))
+
+
+# ---------------------------------------------------------------------------
+# host-only helpers
+# ---------------------------------------------------------------------------
+
+def ns_plan(k: int, method):
+    """(k_eff, levels, products) of the literal schedule."""
+    m = METHODS.get(method, method)
+    ke, lv, g = _I64(), _I32(), _I32()
+    _check(lib.ns_plan(int(k), int(m), ctypes.byref(ke), ctypes.byref(lv), ctypes.byref(g)), "ns_plan")
+    return ke.value, lv.value, g.value
+
+
+def ns_workspace_bytes(n: int, method, dtype) -> int:
+    b = ctypes.c_size_t()
+    _check(lib.ns_workspace_bytes(int(n), int(METHODS.get(method, method)),
+                                  int(DTYPES.get(dtype, dtype)), ctypes.byref(b)),
+           "ns_workspace_bytes")
+    return b.value
+
+
+def ns_radix15_coeffs():
+    """(28 coefficients, prefix error, a15, a16) of the library's radix-15 table."""
+    c = (_D * 28)()
+    pe, s15, s16 = _D(), _D(), _D()
+    _check(lib.ns_radix15_coeffs(c, ctypes.byref(pe), ctypes.byref(s15), ctypes.byref(s16)),
+           "ns_radix15_coeffs")
+    return list(c), pe.value, s15.value, s16.value
+
+
+def ns_status_string(status: int) -> str:
+    return lib.ns_status_string(int(status)).decode()
+
+
+# ---------------------------------------------------------------------------
+# device entry points (torch tensors for memory and streams)
+# ---------------------------------------------------------------------------
+
+class Handle:
+    """Owns an ns_handle (workspace, timing, batched graphs) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.ptr = _P()
+        _check(lib.ns_create(ctypes.byref(self.ptr), int(device)), "ns_create")
+        self.device = device
+
+    def close(self):
+        if self.ptr:
+            lib.ns_destroy(self.ptr)
+            self.ptr = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ns_set_product_timing(self, enable: bool):
+        _check(lib.ns_set_product_timing(self.ptr, int(bool(enable))), "ns_set_product_timing")
+
+    def ns_product_timing(self, reset: bool = True):
+        """(launches, summed kernel ms, summed algorithmic flops) since the last reset."""
+        cnt, ms, fl = _I32(), _D(), _D()
+        _check(lib.ns_product_timing(self.ptr, ctypes.byref(cnt), ctypes.byref(ms),
+                                     ctypes.byref(fl), int(bool(reset))), "ns_product_timing")
+        return cnt.value, ms.value, fl.value
+
+
+_handles = {}
+
+
+def default_handle(device: Optional[int] = None) -> Handle:
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _handles:
+        _handles[dev] = Handle(dev)
+    return _handles[dev]
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _P(stream.cuda_stream)
+
+
+def io_dtype(dtype):
+    """torch element type of A and out for a compute precision."""
+    import torch
+    return torch.float32 if DTYPES.get(dtype, dtype) == F32 else torch.float64
+
+
+def ns_eval_ex(A, k: int, method="radix9", dtype="f64", out=None, handle: Optional[Handle] = None,
+         stream=None, report: bool = False):
+    """S_k(A) for a square CUDA tensor A (row-major, any leading dimension
+    >= n via a 2-D stride).  Returns out (and the report dict if asked)."""
+    import torch
+    m = METHODS.get(method, method)
+    d = DTYPES.get(dtype, dtype)
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square matrix")
+    if A.dtype != io_dtype(d):
+        raise TypeError(f"A must be {io_dtype(d)} for this dtype")
+    if not A.is_cuda or A.stride(1) != 1:
+        raise ValueError("A must be a CUDA tensor with unit column stride")
+    n = A.shape[0]
+    if out is None:
+        out = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    h = handle or default_handle(A.device.index)
+    rep = Report() if report else None
+    _check(lib.ns_eval_ex(h.ptr, _P(A.data_ptr()), n, A.stride(0), int(k), int(m), int(d),
+                          _P(out.data_ptr()), out.stride(0), _stream_ptr(stream),
+                          ctypes.byref(rep) if rep is not None else None), "ns_eval_ex")
+    return (out, rep.as_dict()) if report else out
+
+
+def ns_eval(A, k: int, method="radix9", dtype="f64", out=None):
+    """The short form (per-device default handle, null stream, lda = n)."""
+    import torch
+    m, d = METHODS.get(method, method), DTYPES.get(dtype, dtype)
+    if out is None:
+        out = torch.empty_like(A)
+    _check(lib.ns_eval(_P(A.data_ptr()), A.shape[0], int(k), int(m), int(d), _P(out.data_ptr())),
+           "ns_eval")
+    return out
+
+
+def ns_eval_batched(A_packed, offsets_dev, n_dev, n_host, k: int, method="radix9", dtype="f32",
+                 out_packed=None, handle: Optional[Handle] = None, stream=None,
+                 report: bool = False):
+    """Batched S_k over packed row-major float32 matrices (see ns.h)."""
+    import torch
+    h = handle or default_handle(A_packed.device.index)
+    if out_packed is None:
+        out_packed = torch.empty_like(A_packed)
+    n_host = n_host.to(torch.int32).contiguous().cpu()
+    rep = Report() if report else None
+    _check(lib.ns_eval_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
+                               _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host), int(k),
+                               int(METHODS.get(method, method)), int(DTYPES.get(dtype, dtype)),
+                               _P(out_packed.data_ptr()), _stream_ptr(stream),
+                               ctypes.byref(rep) if rep is not None else None),
+           "ns_eval_batched")
+    return (out_packed, rep.as_dict()) if report else out_packed
+
+
+def ns_eval_batched_loop(A_packed, offsets_host, n_host, k: int, method="radix9", dtype="f32",
+                      out_packed=None, handle: Optional[Handle] = None, stream=None):
+    """The per-matrix launch loop over the same packed layout."""
+    import torch
+    h = handle or default_handle(A_packed.device.index)
+    if out_packed is None:
+        out_packed = torch.empty_like(A_packed)
+    offs = offsets_host.to(torch.int64).contiguous().cpu()
+    n_host = n_host.to(torch.int32).contiguous().cpu()
+    _check(lib.ns_eval_batched_loop(h.ptr, _P(A_packed.data_ptr()), _P(offs.data_ptr()),
+                                    _P(n_host.data_ptr()), len(n_host), int(k),
+                                    int(METHODS.get(method, method)),
+                                    int(DTYPES.get(dtype, dtype)), _P(out_packed.data_ptr()),
+                                    _stream_ptr(stream)), "ns_eval_batched_loop")
+    return out_packed
+
+
+def ns_autotune_batched(A_packed, offsets_dev, n_dev, n_host, k: int, out_packed,
+                     handle: Optional[Handle] = None, stream=None) -> int:
+    import torch
+    h = handle or default_handle(A_packed.device.index)
+    n_host = n_host.to(torch.int32).contiguous().cpu()
+    cnt = _I32()
+    _check(lib.ns_autotune_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
+                                   _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host),
+                                   int(k), _P(out_packed.data_ptr()), _stream_ptr(stream),
+                                   ctypes.byref(cnt)), "ns_autotune_batched")
+    return cnt.value

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host scheduler and the HIP kernels.
+// Not part of the public ABI (include/ns.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ns {
+
+constexpr int kMaxZ = 3;     // epilogue inputs per product
+constexpr int kMaxOut = 6;   // epilogue outputs per product
+
+// One epilogue output:  out = a * (X Y) + sum_i z[i] * Z_i + id * I
+struct EpiOut {
+  void* ptr;
+  int f64;                   // element type of ptr: 1 double, 0 float
+  double a;
+  double z[kMaxZ];
+  double id;
+};
+
+// Operand storage / arithmetic of a product launch.
+enum Engine : int {
+  ENG_F64 = 0,        // double operands, FP64 MFMA 4x4x4
+  ENG_F32 = 1,        // float operands, FP32 MFMA 16x16x4
+  ENG_BF16X3 = 2,     // float operands split to bf16 hi/lo, 3 BF16 MFMA products
+  ENG_F16S = 3,       // float operands scaled by 2^-e and rounded to fp16, 1 FP16 MFMA product
+};
+
+// Parameters of one n x n x n product C = X Y with a fused multi-output
+// epilogue.  All buffers are row-major with leading dimension ld (= the
+// internal, tile-padded n).
+struct GemmParams {
+  const void* X;
+  const void* Y;
+  int n;                      // padded dimension (multiple of the tile size)
+  int ld;
+  int nz;
+  const void* Z[kMaxZ];
+  int zf64[kMaxZ];
+  int no;
+  EpiOut out[kMaxOut];
+  double* sumsq;              // if non-null: += sum of squares of output 0
+  int* nonfinite;             // if non-null: set to 1 if any output 0 entry is Inf/NaN
+  unsigned* amax;             // if non-null: atomicMax of |output 0| as float bits
+  const unsigned* xamax;      // low-precision engines: max-abs of X (float bits) for scaling
+  const unsigned* yamax;      // ... of Y
+};
+
+// Tile-size requirement of each engine for a given n (the padded n must be a
+// multiple of it).  Small n use smaller tiles.
+int engine_tile(Engine e, int n);
+
+// Launch one product on `stream`.  Returns hipSuccess or the launch error.
+hipError_t launch_gemm(Engine e, const GemmParams& p, hipStream_t stream);
+
+// Elementwise helpers (util.hip).
+// dst (padded n_pad x n_pad, ld n_pad) <- src (n x n, lda) converted; the
+// padding is zero.  *_f64 flags give element types.
+hipError_t launch_pad_copy(const void* src, int src_f64, int64_t n, int64_t lda,
+                           void* dst, int dst_f64, int n_pad, hipStream_t s);
+// dst (n x n, ldo) <- top-left n x n block of src (ld n_pad).
+hipError_t launch_unpad_copy(const void* src, int src_f64, int n_pad, void* dst, int dst_f64,
+                             int64_t n, int64_t ldo, hipStream_t s);
+// dst <- identity (padded), element type by flag.
+hipError_t launch_set_identity(void* dst, int f64, int n_pad, hipStream_t s);
+// Fill `count` doubles / ints / unsigned with zero (a kernel, not a memset).
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
+// max-abs of a float matrix into *amax (float bits), atomically.
+hipError_t launch_amax(const float* x, size_t count, unsigned* amax, hipStream_t s);
+
+}  // namespace ns

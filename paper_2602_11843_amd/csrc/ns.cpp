@@ -1,0 +1,747 @@
+// libns host side: argument checking, workspace, the series schedules and the
+// C ABI of include/ns.h.
+//
+// Every schedule below is a sequence of n x n x n products issued to the
+// engines of gemm.hip; each product carries the linear combinations the
+// paper's circuit needs next as extra epilogue outputs, so the only device
+// work between products is the products themselves.
+//
+// Schedules use the "increment" form of the updates, algebraically identical
+// to the paper's and better conditioned in low precision:
+//   S_{mn} = S_n T            ->  S += S (T - I)
+//   A^{mn} = I - T + T A^n    ->  B  = B - (T - I) + (T - I) B
+//   Y_{n+1} = Y_n f(R_n)      ->  Y += Y (f(R) - I)
+//   R_{n+1} = I - (I - A) Y   ->  R  = I - Y + A Y
+// so T - I (or f(R) - I) is formed instead of T.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ns.h"
+#include "common.h"
+
+namespace ns {
+bool radix15_table(double c[28], double* prefix_err, double* s15, double* s16);
+int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, const int32_t* n_dev,
+                 const int32_t* n_host, int32_t batch, int64_t k, int method, int dtype,
+                 void* out_packed, hipStream_t stream, ns_report* rep);
+int batched_autotune(ns_handle* h, const void* A_packed, const int64_t* off_dev,
+                     const int32_t* n_dev, const int32_t* n_host, int32_t batch, int64_t k,
+                     void* out_packed, hipStream_t stream, int32_t* n_timed);
+void batched_release(ns_handle* h);
+}  // namespace ns
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define NS_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(NS_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                               \
+  } while (0)
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct ns_handle {
+  int device = 0;
+  void* ws = nullptr;            // workspace arena
+  size_t ws_bytes = 0;
+  // timing of product launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev;    // pairs (start, stop)
+  size_t ev_used = 0;
+  double flops_logged = 0.0;
+  // batched state (owned by batched.hip)
+  void* batched = nullptr;
+};
+
+namespace ns {
+namespace {
+
+constexpr int kScalarBytes = 64 * 1024;   // norms, flags and max-abs slots
+constexpr int kAmaxSlots = 8192;
+
+struct Scalars {                          // layout of the scalar block in device memory
+  double level_sumsq[NS_MAX_LEVELS];
+  int nonfinite;
+  int pad;
+  unsigned amax[kAmaxSlots];
+};
+static_assert(sizeof(Scalars) <= kScalarBytes, "scalar block too small");
+
+bool is_mixed(int dtype) {
+  return dtype == NS_SPLIT_BF16 || dtype == NS_F16_SCALED || dtype == NS_F32_ACC64;
+}
+bool is_residual(int method) {
+  return method == NS_RADIX15 || method == NS_RADIX9_RESID || method == NS_HENSEL;
+}
+Engine work_engine(int dtype) {
+  switch (dtype) {
+    case NS_F64: return ENG_F64;
+    case NS_F32: return ENG_F32;
+    case NS_SPLIT_BF16: return ENG_BF16X3;
+    case NS_F16_SCALED: return ENG_F16S;
+    default: return ENG_F32;
+  }
+}
+
+int radix_of(int method) {
+  switch (method) {
+    case NS_BINARY: return 2;
+    case NS_TERNARY: return 3;
+    case NS_QUINARY: return 5;
+    case NS_RADIX9: case NS_RADIX9_RESID: return 9;
+    case NS_RADIX15: return 15;
+    case NS_HENSEL: return 2;
+    default: return 0;
+  }
+}
+// products per level: mu_m + 2 (Sec. 2.2 cost model; Sec. 5.4 eq. (9))
+int per_level(int method) {
+  switch (method) {
+    case NS_BINARY: return 2;
+    case NS_TERNARY: return 3;
+    case NS_QUINARY: return 4;
+    case NS_RADIX9: case NS_RADIX9_RESID: return 5;
+    case NS_RADIX15: return 6;
+    case NS_HENSEL: return 2;
+    default: return 0;
+  }
+}
+
+int plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gemms) {
+  if (k < 1) return fail(NS_ERR_ARG, "k must be >= 1 (got %lld)", (long long)k);
+  if (method == NS_NAIVE) {
+    if (k - 1 > INT32_MAX) return fail(NS_ERR_RANGE, "naive k too large");
+    *k_eff = k;
+    *levels = (int32_t)(k - 1);
+    *gemms = (int32_t)(k - 1);
+    return NS_OK;
+  }
+  const int m = radix_of(method);
+  if (m == 0) return fail(NS_ERR_ARG, "unknown method %d", method);
+  int t = 0;
+  __int128 p = 1;
+  while (p < k) {
+    p *= m;
+    ++t;
+  }
+  if (p > INT64_MAX || t > NS_MAX_LEVELS)
+    return fail(NS_ERR_RANGE, "k_eff = %d^%d overflows", m, t);
+  *k_eff = (int64_t)p;
+  *levels = t;
+  *gemms = per_level(method) * t;
+  return NS_OK;
+}
+
+int n_internal(int64_t n, int dtype) {
+  const Engine e = work_engine(dtype);
+  int t = engine_tile(e, (int)n);
+  if (is_mixed(dtype)) t = std::max(t, engine_tile(ENG_F64, (int)n));
+  int np = (int)((n + t - 1) / t * t);
+  // the tile choice depends on the padded size; re-round if it changed
+  int t2 = engine_tile(e, np);
+  if (is_mixed(dtype)) t2 = std::max(t2, engine_tile(ENG_F64, np));
+  return (int)((np + t2 - 1) / t2 * t2);
+}
+
+// working-precision buffers and FP64 accumulators each schedule needs
+void buffer_counts(int method, int dtype, int* nw, int* n64) {
+  const bool mixed = is_mixed(dtype);
+  switch (method) {
+    case NS_NAIVE: *nw = 3; break;                       // A, S, S'
+    case NS_BINARY: *nw = 4; break;                      // S, S', P, P'
+    case NS_TERNARY: *nw = 6; break;                     // S, S', P, P2, P', T
+    case NS_QUINARY: *nw = 7; break;                     // S, S', B, B', U, X1, T
+    case NS_RADIX9: *nw = 9; break;                      // S, S', B, B', U, X1, P, Q, T
+    case NS_HENSEL: *nw = 4; break;                      // A, R, Y, Y'
+    case NS_RADIX9_RESID: *nw = 9; break;                // A, R, Y, Y', U, X1, P, Q, T
+    case NS_RADIX15: *nw = 12; break;                    // A, R, Y, Y', P1, L2, R2, L3, R3, L4, R4, F
+    default: *nw = 0;
+  }
+  *n64 = mixed ? (is_residual(method) ? 2 : 1) : 0;    // Y64 + A64, or S64
+}
+
+size_t workspace_bytes(int64_t n, int method, int dtype) {
+  const int np = n_internal(n, dtype);
+  int nw, n64;
+  buffer_counts(method, dtype, &nw, &n64);
+  const size_t w = (dtype == NS_F64) ? 8 : 4;
+  const size_t mat = (size_t)np * np;
+  return kScalarBytes + mat * (nw * w + n64 * 8) + 256 * (nw + n64 + 1);
+}
+
+// ---------------------------------------------------------------------------
+// execution context
+// ---------------------------------------------------------------------------
+struct Buf {
+  void* p = nullptr;
+  int f64 = 0;
+  unsigned* amax = nullptr;   // max-abs slot of the current contents (scaled FP16)
+};
+
+struct Out {
+  Buf* b;
+  double a;
+  double z[kMaxZ];
+  double id;
+};
+
+struct Ctx {
+  ns_handle* h;
+  hipStream_t s;
+  int n;              // caller's n
+  int np;             // internal n
+  Engine eng;         // working engine
+  bool mixed;
+  Scalars* scal;      // device
+  int next_amax = 0;
+  int gemms = 0;
+  int status = NS_OK;
+  char* arena;
+  size_t arena_off = 0;
+
+  Buf take(int f64) {
+    Buf b;
+    b.p = arena + arena_off;
+    b.f64 = f64;
+    arena_off += (size_t)np * np * (f64 ? 8 : 4);
+    arena_off = (arena_off + 255) & ~(size_t)255;
+    return b;
+  }
+
+  // C = X Y on engine e; Z inputs; outputs as affine combinations of
+  // (C, Z..., I).  norm_level >= 0 accumulates ||output 0||_F^2 there.
+  void gemm(Engine e, const Buf& X, const Buf& Y, std::initializer_list<Buf> Z,
+            std::initializer_list<Out> outs, int norm_level = -1) {
+    if (status != NS_OK) return;
+    GemmParams p{};
+    p.X = X.p;
+    p.Y = Y.p;
+    p.n = np;
+    p.ld = np;
+    p.nz = 0;
+    for (const Buf& z : Z) {
+      p.Z[p.nz] = z.p;
+      p.zf64[p.nz] = z.f64;
+      ++p.nz;
+    }
+    p.no = 0;
+    for (const Out& o : outs) {
+      EpiOut& e_ = p.out[p.no++];
+      e_.ptr = o.b->p;
+      e_.f64 = o.b->f64;
+      e_.a = o.a;
+      for (int i = 0; i < kMaxZ; ++i) e_.z[i] = o.z[i];
+      e_.id = o.id;
+    }
+    p.sumsq = norm_level >= 0 ? &scal->level_sumsq[norm_level] : nullptr;
+    p.nonfinite = &scal->nonfinite;
+    if (eng == ENG_F16S) {
+      // the scaled-FP16 engine needs each operand's max-abs: output 0 records it
+      if (next_amax >= kAmaxSlots) {
+        status = fail(NS_ERR_RANGE, "too many products for the max-abs slots");
+        return;
+      }
+      p.amax = &scal->amax[next_amax++];
+      p.xamax = X.amax;
+      p.yamax = Y.amax;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing) {
+      if (h->ev_used + 2 > h->ev.size()) {
+        for (int i = 0; i < 64; ++i) {
+          hipEvent_t ev;
+          if (hipEventCreate(&ev) != hipSuccess) {
+            status = fail(NS_ERR_HIP, "hipEventCreate failed");
+            return;
+          }
+          h->ev.push_back(ev);
+        }
+      }
+      e0 = h->ev[h->ev_used];
+      e1 = h->ev[h->ev_used + 1];
+      h->ev_used += 2;
+      hipEventRecord(e0, s);
+    }
+    const hipError_t err = launch_gemm(e, p, s);
+    if (h->timing) {
+      hipEventRecord(e1, s);
+      h->flops_logged += 2.0 * (double)n * n * n;
+    }
+    if (err != hipSuccess) {
+      status = fail(NS_ERR_HIP, "product launch failed: %s", hipGetErrorString(err));
+      return;
+    }
+    ++gemms;
+    if (p.amax) {
+      // every output of this product is a combination whose magnitude the
+      // epilogue bounds only for output 0; the remaining outputs get their own
+      // max-abs pass right away (they are the next products' operands)
+      for (size_t i = 0; i < outs.size(); ++i) {
+        Buf* b = (outs.begin() + i)->b;
+        if (i == 0) {
+          b->amax = p.amax;
+        } else {
+          if (next_amax >= kAmaxSlots) {
+            status = fail(NS_ERR_RANGE, "too many max-abs slots");
+            return;
+          }
+          b->amax = &scal->amax[next_amax++];
+          if (!b->f64) launch_amax(static_cast<const float*>(b->p), (size_t)np * np, b->amax, s);
+        }
+      }
+    }
+  }
+};
+
+Out o(Buf& b, double a, double z0 = 0, double z1 = 0, double z2 = 0, double id = 0) {
+  return Out{&b, a, {z0, z1, z2}, id};
+}
+
+// ---------------------------------------------------------------------------
+// schedules
+// ---------------------------------------------------------------------------
+
+// Running sum update S <- S + S (T - I)  (block concatenation, eq. (2)).
+// Sw is the working-precision operand; S64 (mixed forms) the FP64 accumulator.
+void sum_update(Ctx& c, Buf& Sw, Buf& Sw2, Buf* S64, Buf& Tm1) {
+  if (S64) {
+    c.gemm(c.eng, Sw, Tm1, {*S64}, {o(*S64, 1, 1), o(Sw2, 1, 1)});
+  } else {
+    c.gemm(c.eng, Sw, Tm1, {Sw}, {o(Sw2, 1, 1)});
+  }
+  std::swap(Sw, Sw2);
+}
+
+// Theorem 3.1 on B: after the three products T holds T9(B) - I.
+//   U = B^2;  V = U (B + 2U);  P = 3/20 B + 2U + V;  Q = 11/40 B - 1/8 U + 1/4 V;
+//   W = P Q;  T9 = W + I + B + 767/800 U + 15/32 V.
+void kernel_radix9(Ctx& c, Buf& B, Buf& U, Buf& X1, Buf& P, Buf& Q, Buf& T) {
+  c.gemm(c.eng, B, B, {B},
+         {o(U, 1.0), o(X1, 2.0, 1.0), o(P, 2.0, 3.0 / 20.0), o(Q, -1.0 / 8.0, 11.0 / 40.0),
+          o(T, 767.0 / 800.0, 1.0)});
+  c.gemm(c.eng, U, X1, {P, Q, T}, {o(P, 1.0, 1.0), o(Q, 0.25, 0, 1.0), o(T, 15.0 / 32.0, 0, 0, 1.0)});
+  c.gemm(c.eng, P, Q, {T}, {o(T, 1.0, 1.0)});
+}
+
+// Gustafsson's quinary kernel (Sec. 2.3): U = B^2, V = U (B + U),
+// T5 = I + B + U + V; T holds T5 - I.
+void kernel_quinary(Ctx& c, Buf& B, Buf& U, Buf& X1, Buf& T) {
+  c.gemm(c.eng, B, B, {B}, {o(U, 1.0), o(X1, 1.0, 1.0), o(T, 1.0, 1.0)});
+  c.gemm(c.eng, U, X1, {T}, {o(T, 1.0, 1.0)});
+}
+
+// Sec. 4.1 eq. (4)-(5) on R with coefficients k[28]; F holds T15~(R) - I.
+void kernel_radix15(Ctx& c, const double* k, Buf& R, Buf& P1, Buf& L2, Buf& R2, Buf& L3,
+                    Buf& R3, Buf& L4, Buf& R4, Buf& F) {
+  const double *l2 = k, *r2 = k + 3, *l3 = k + 6, *r3 = k + 10, *l4 = k + 14, *r4 = k + 19,
+               *g = k + 24;
+  // P1 = R R; the factors of P2 are combinations of {I, R, P1}
+  c.gemm(c.eng, R, R, {R},
+         {o(P1, 1.0), o(L2, l2[2], l2[1], 0, 0, l2[0]), o(R2, r2[2], r2[1], 0, 0, r2[0])});
+  // P2 = L2 R2; factors of P3 complete, those of P4 and F partial
+  c.gemm(c.eng, L2, R2, {R, P1},
+         {o(L3, l3[3], l3[1], l3[2], 0, l3[0]), o(R3, r3[3], r3[1], r3[2], 0, r3[0]),
+          o(L4, l4[3], l4[1], l4[2], 0, l4[0]), o(R4, r4[3], r4[1], r4[2], 0, r4[0]),
+          o(F, g[2], g[0], g[1])});
+  // P3 = L3 R3
+  c.gemm(c.eng, L3, R3, {L4, R4, F}, {o(L4, l4[4], 1.0), o(R4, r4[4], 0, 1.0), o(F, g[3], 0, 0, 1.0)});
+  // P4 = L4 R4
+  c.gemm(c.eng, L4, R4, {F}, {o(F, 1.0, 1.0)});
+}
+
+struct Result {
+  Buf S;          // what to copy out (FP64 accumulator for mixed forms)
+};
+
+int run_schedule(Ctx& c, int method, int levels, const Buf& Ain_w, const Buf* Ain64,
+                 Result* res) {
+  const int W64 = (c.eng == ENG_F64) ? 1 : 0;
+  Buf A = Ain_w;
+  switch (method) {
+    case NS_NAIVE: {                                   // S <- I + A S
+      Buf S = c.take(W64), S2 = c.take(W64);
+      launch_set_identity(S.p, W64, c.np, c.s);
+      for (int i = 0; i < levels; ++i) {
+        c.gemm(c.eng, A, S, {}, {o(S2, 1.0, 0, 0, 0, 1.0)});
+        std::swap(S, S2);
+      }
+      res->S = S;
+      break;
+    }
+    case NS_BINARY:
+    case NS_TERNARY:
+    case NS_QUINARY:
+    case NS_RADIX9: {
+      Buf S = c.take(W64), S2 = c.take(W64), B = A, B2 = c.take(W64);
+      Buf S64;
+      if (c.mixed) {
+        S64 = c.take(1);
+        launch_set_identity(S64.p, 1, c.np, c.s);
+      }
+      launch_set_identity(S.p, W64, c.np, c.s);
+      Buf U, X1, P, Q, T;
+      if (method == NS_RADIX9) { U = c.take(W64); X1 = c.take(W64); P = c.take(W64); Q = c.take(W64); T = c.take(W64); }
+      if (method == NS_QUINARY) { U = c.take(W64); X1 = c.take(W64); T = c.take(W64); }
+      if (method == NS_TERNARY) { U = c.take(W64); T = c.take(W64); }
+      for (int lv = 0; lv < levels && c.status == NS_OK; ++lv) {
+        if (method == NS_BINARY) {
+          // S_2n = S_n (I + A^n);  A^2n = A^n A^n
+          sum_update(c, S, S2, c.mixed ? &S64 : nullptr, B);
+          c.gemm(c.eng, B, B, {}, {o(B2, 1.0)}, lv);
+          std::swap(B, B2);
+          continue;
+        }
+        if (method == NS_TERNARY) {
+          // A^2n = A^n A^n;  A^3n = A^2n A^n;  S_3n = S_n (I + A^n + A^2n)
+          c.gemm(c.eng, B, B, {B}, {o(U, 1.0), o(T, 1.0, 1.0)});
+          c.gemm(c.eng, U, B, {}, {o(B2, 1.0)}, lv);
+          sum_update(c, S, S2, c.mixed ? &S64 : nullptr, T);
+          std::swap(B, B2);
+          continue;
+        }
+        if (method == NS_RADIX9) kernel_radix9(c, B, U, X1, P, Q, T);
+        else kernel_quinary(c, B, U, X1, T);
+        sum_update(c, S, S2, c.mixed ? &S64 : nullptr, T);
+        // telescoping: A^{mn} = I - T + T A^n = B - (T - I) + (T - I) B
+        c.gemm(c.eng, T, B, {B, T}, {o(B2, 1.0, 1.0, -1.0)}, lv);
+        std::swap(B, B2);   // after the first level the copy of A becomes the spare
+      }
+      res->S = c.mixed ? S64 : S;
+      break;
+    }
+    case NS_HENSEL:
+    case NS_RADIX9_RESID:
+    case NS_RADIX15: {
+      // Y_0 = I, R_0 = A;  Y <- Y f(R);  R <- I - (I - A) Y   (eq. (8))
+      Buf Y = c.take(W64), Y2 = c.take(W64), R = c.take(W64);
+      Buf Y64, A64;
+      launch_set_identity(Y.p, W64, c.np, c.s);
+      if (c.mixed) {
+        Y64 = c.take(1);
+        launch_set_identity(Y64.p, 1, c.np, c.s);
+        A64 = *Ain64;
+      }
+      // R_0 = A: the first level reads the copy of A directly
+      Buf Rcur = A;
+      double k15[28];
+      Buf U, X1, P, Q, T, P1, L2, R2, L3, R3, L4, R4, F;
+      if (method == NS_RADIX9_RESID) { U = c.take(W64); X1 = c.take(W64); P = c.take(W64); Q = c.take(W64); T = c.take(W64); }
+      if (method == NS_RADIX15) {
+        radix15_table(k15, nullptr, nullptr, nullptr);
+        P1 = c.take(W64); L2 = c.take(W64); R2 = c.take(W64); L3 = c.take(W64);
+        R3 = c.take(W64); L4 = c.take(W64); R4 = c.take(W64); F = c.take(W64);
+      }
+      for (int lv = 0; lv < levels && c.status == NS_OK; ++lv) {
+        Buf* Fm1;
+        if (method == NS_HENSEL) Fm1 = &Rcur;                        // f(R) - I = R
+        else if (method == NS_RADIX9_RESID) { kernel_radix9(c, Rcur, U, X1, P, Q, T); Fm1 = &T; }
+        else { kernel_radix15(c, k15, Rcur, P1, L2, R2, L3, R3, L4, R4, F); Fm1 = &F; }
+        sum_update(c, Y, Y2, c.mixed ? &Y64 : nullptr, *Fm1);
+        // R = I - Y + A Y: the true residual of the new iterate
+        if (c.mixed) c.gemm(ENG_F64, A64, Y64, {Y64}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
+        else c.gemm(c.eng, A, Y, {Y}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
+        Rcur = R;
+      }
+      res->S = c.mixed ? Y64 : Y;
+      break;
+    }
+    default:
+      return fail(NS_ERR_ARG, "unknown method %d", method);
+  }
+  return c.status;
+}
+
+int check_args(const void* A, int64_t n, int64_t lda, int64_t k, int method, int dtype,
+               const void* out, int64_t ldo) {
+  if (!A || !out) return fail(NS_ERR_ARG, "null matrix pointer");
+  if (n <= 0) return fail(NS_ERR_ARG, "n must be positive (got %lld)", (long long)n);
+  if (n > 65536) return fail(NS_ERR_RANGE, "n = %lld above the supported 65536", (long long)n);
+  if (lda < n || ldo < n) return fail(NS_ERR_ARG, "leading dimension below n");
+  if (k < 1) return fail(NS_ERR_ARG, "k must be >= 1 (got %lld)", (long long)k);
+  if (method < NS_NAIVE || method > NS_HENSEL) return fail(NS_ERR_ARG, "unknown method %d", method);
+  if (dtype < NS_F64 || dtype > NS_F32_ACC64) return fail(NS_ERR_ARG, "unknown dtype %d", dtype);
+  if (method == NS_NAIVE && is_mixed(dtype))
+    return fail(NS_ERR_UNSUPPORTED, "the naive Horner form has no FP64-accumulated variant");
+  const size_t es = (dtype == NS_F32) ? 4 : 8;
+  const char* a0 = static_cast<const char*>(A);
+  const char* a1 = a0 + ((size_t)(n - 1) * lda + n) * es;
+  const char* b0 = static_cast<const char*>(out);
+  const char* b1 = b0 + ((size_t)(n - 1) * ldo + n) * es;
+  if (a0 < b1 && b0 < a1) return fail(NS_ERR_ARG, "out overlaps A");
+  return NS_OK;
+}
+
+int ensure_workspace(ns_handle* h, size_t bytes) {
+  if (h->ws_bytes >= bytes) return NS_OK;
+  if (h->ws) {
+    NS_HIP(hipDeviceSynchronize());
+    NS_HIP(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  if (hipMalloc(&h->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    h->ws = nullptr;
+    return fail(NS_ERR_NOMEM, "workspace of %zu bytes could not be allocated", bytes);
+  }
+  h->ws_bytes = bytes;
+  return NS_OK;
+}
+
+std::mutex g_default_mu;
+ns_handle* g_default[64] = {};
+
+}  // namespace
+
+int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, int method,
+              int dtype, void* out, int64_t ldo, hipStream_t s, ns_report* rep) {
+  int st = check_args(A, n, lda, k, method, dtype, out, ldo);
+  if (st) return st;
+  int64_t k_eff;
+  int32_t levels, gemms_formula;
+  if ((st = plan(k, method, &k_eff, &levels, &gemms_formula))) return st;
+  NS_HIP(hipSetDevice(h->device));
+  if ((st = ensure_workspace(h, workspace_bytes(n, method, dtype)))) return st;
+
+  Ctx c{};
+  c.h = h;
+  c.s = s;
+  c.n = (int)n;
+  c.np = n_internal(n, dtype);
+  c.eng = work_engine(dtype);
+  c.mixed = is_mixed(dtype);
+  c.scal = static_cast<Scalars*>(h->ws);
+  c.arena = static_cast<char*>(h->ws) + kScalarBytes;
+  NS_HIP(launch_zero_words(c.scal, sizeof(Scalars), s));
+
+  const int in64 = (dtype != NS_F32);
+  const int W64 = (c.eng == ENG_F64);
+  Buf Aw = c.take(W64);
+  NS_HIP(launch_pad_copy(A, in64, n, lda, Aw.p, W64, c.np, s));
+  Buf A64;
+  if (c.mixed && is_residual(method)) {
+    A64 = c.take(1);
+    NS_HIP(launch_pad_copy(A, 1, n, lda, A64.p, 1, c.np, s));
+  }
+  if (c.eng == ENG_F16S) {
+    Aw.amax = &c.scal->amax[c.next_amax++];
+    NS_HIP(launch_amax(static_cast<const float*>(Aw.p), (size_t)c.np * c.np, Aw.amax, s));
+  }
+  Result res;
+  if ((st = run_schedule(c, method, levels, Aw, c.mixed ? &A64 : nullptr, &res))) return st;
+  const int out64 = in64;
+  NS_HIP(launch_unpad_copy(res.S.p, res.S.f64, c.np, out, out64, n, ldo, s));
+
+  if (rep) {
+    Scalars hs;
+    NS_HIP(hipMemcpyAsync(&hs, c.scal, offsetof(Scalars, amax), hipMemcpyDeviceToHost, s));
+    NS_HIP(hipStreamSynchronize(s));
+    std::memset(rep, 0, sizeof(*rep));
+    rep->k_eff = k_eff;
+    rep->levels = levels;
+    rep->gemms_performed = c.gemms;
+    rep->gemms_formula = gemms_formula;
+    rep->nonfinite = hs.nonfinite ? 1 : 0;
+    rep->n_internal = c.np;
+    rep->method = method;
+    rep->dtype = dtype;
+    if (method != NS_NAIVE)
+      for (int i = 0; i < levels && i < NS_MAX_LEVELS; ++i) rep->level_norm[i] = std::sqrt(hs.level_sumsq[i]);
+    if (method == NS_RADIX15) {
+      double cc[28];
+      radix15_table(cc, &rep->kernel_prefix_err, &rep->spill15, &rep->spill16);
+    }
+  }
+  return NS_OK;
+}
+
+}  // namespace ns
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int ns_create(ns_handle** h, int device) {
+  if (!h) return fail(NS_ERR_ARG, "null handle pointer");
+  *h = nullptr;
+  int count = 0;
+  NS_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(NS_ERR_ARG, "device %d of %d", device, count);
+  ns_handle* p = new (std::nothrow) ns_handle();
+  if (!p) return fail(NS_ERR_NOMEM, "host allocation failed");
+  p->device = device;
+  *h = p;
+  return NS_OK;
+}
+
+int ns_destroy(ns_handle* h) {
+  if (!h) return NS_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  ns::batched_release(h);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->ws) (void)hipFree(h->ws);
+  delete h;
+  return NS_OK;
+}
+
+int ns_plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gemms) {
+  int64_t a;
+  int32_t b, c;
+  const int st = ns::plan(k, method, &a, &b, &c);
+  if (st) return st;
+  if (k_eff) *k_eff = a;
+  if (levels) *levels = b;
+  if (gemms) *gemms = c;
+  return NS_OK;
+}
+
+int ns_workspace_bytes(int64_t n, int method, int dtype, size_t* bytes) {
+  if (!bytes) return fail(NS_ERR_ARG, "null output pointer");
+  if (n <= 0 || method < NS_NAIVE || method > NS_HENSEL || dtype < NS_F64 || dtype > NS_F32_ACC64)
+    return fail(NS_ERR_ARG, "bad arguments");
+  *bytes = ns::workspace_bytes(n, method, dtype);
+  return NS_OK;
+}
+
+int ns_eval_ex(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, int method,
+               int dtype, void* out, int64_t ldo, hipStream_t stream, ns_report* rep) {
+  if (!h) return fail(NS_ERR_ARG, "null handle");
+  try {
+    return ns::eval_impl(h, A, n, lda, k, method, dtype, out, ldo, stream, rep);
+  } catch (...) {
+    return fail(NS_ERR_HIP, "unexpected C++ exception");
+  }
+}
+
+int ns_eval(const void* A, int64_t n, int64_t k, int method, int dtype, void* out) {
+  int dev = 0;
+  NS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(NS_ERR_ARG, "device index %d", dev);
+  ns_handle* h;
+  {
+    std::lock_guard<std::mutex> lk(ns::g_default_mu);
+    if (!ns::g_default[dev]) {
+      const int st = ns_create(&ns::g_default[dev], dev);
+      if (st) return st;
+    }
+    h = ns::g_default[dev];
+  }
+  return ns_eval_ex(h, A, n, n, k, method, dtype, out, n, nullptr, nullptr);
+}
+
+int ns_eval_batched(ns_handle* h, const void* A_packed, const int64_t* off_dev,
+                    const int32_t* n_dev, const int32_t* n_host, int32_t batch, int64_t k,
+                    int method, int dtype, void* out_packed, hipStream_t stream, ns_report* rep) {
+  if (!h) return fail(NS_ERR_ARG, "null handle");
+  try {
+    return ns::batched_eval(h, A_packed, off_dev, n_dev, n_host, batch, k, method, dtype,
+                            out_packed, stream, rep);
+  } catch (...) {
+    return fail(NS_ERR_HIP, "unexpected C++ exception");
+  }
+}
+
+int ns_eval_batched_loop(ns_handle* h, const void* A_packed, const int64_t* off_host,
+                         const int32_t* n_host, int32_t batch, int64_t k, int method, int dtype,
+                         void* out_packed, hipStream_t stream) {
+  if (!h || !A_packed || !off_host || !n_host || !out_packed || batch < 0)
+    return fail(NS_ERR_ARG, "bad arguments");
+  if (dtype != NS_F32) return fail(NS_ERR_UNSUPPORTED, "the batched forms are FP32");
+  for (int32_t i = 0; i < batch; ++i) {
+    const float* a = static_cast<const float*>(A_packed) + off_host[i];
+    float* o = static_cast<float*>(out_packed) + off_host[i];
+    const int st = ns_eval_ex(h, a, n_host[i], n_host[i], k, method, dtype, o, n_host[i], stream, nullptr);
+    if (st) return st;
+  }
+  return NS_OK;
+}
+
+int ns_autotune_batched(ns_handle* h, const void* A_packed, const int64_t* off_dev,
+                        const int32_t* n_dev, const int32_t* n_host, int32_t batch, int64_t k,
+                        void* out_packed, hipStream_t stream, int32_t* n_timed) {
+  if (!h) return fail(NS_ERR_ARG, "null handle");
+  try {
+    return ns::batched_autotune(h, A_packed, off_dev, n_dev, n_host, batch, k, out_packed, stream,
+                                n_timed);
+  } catch (...) {
+    return fail(NS_ERR_HIP, "unexpected C++ exception");
+  }
+}
+
+int ns_radix15_coeffs(double c28[28], double* prefix_err, double* spill15, double* spill16) {
+  if (!c28) return fail(NS_ERR_ARG, "null output");
+  if (!ns::radix15_table(c28, prefix_err, spill15, spill16))
+    return fail(NS_ERR_RANGE, "radix-15 coefficient polish did not converge");
+  return NS_OK;
+}
+
+int ns_set_product_timing(ns_handle* h, int enable) {
+  if (!h) return fail(NS_ERR_ARG, "null handle");
+  h->timing = enable != 0;
+  return NS_OK;
+}
+
+int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* total_flops,
+                      int reset) {
+  if (!h) return fail(NS_ERR_ARG, "null handle");
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    NS_HIP(hipEventSynchronize(h->ev[i + 1]));
+    float t = 0.f;
+    NS_HIP(hipEventElapsedTime(&t, h->ev[i], h->ev[i + 1]));
+    ms += t;
+  }
+  if (count) *count = (int32_t)(h->ev_used / 2);
+  if (total_ms) *total_ms = ms;
+  if (total_flops) *total_flops = h->flops_logged;
+  if (reset) {
+    h->ev_used = 0;
+    h->flops_logged = 0.0;
+  }
+  return NS_OK;
+}
+
+const char* ns_status_string(int status) {
+  switch (status) {
+    case NS_OK: return "ok";
+    case NS_ERR_ARG: return "invalid argument";
+    case NS_ERR_UNSUPPORTED: return "unsupported combination";
+    case NS_ERR_NOMEM: return "out of device memory";
+    case NS_ERR_HIP: return "HIP runtime error";
+    case NS_ERR_RANGE: return "size out of range";
+    default: return "unknown status";
+  }
+}
+
+const char* ns_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+// Radix-15 kernel coefficients for the four-product circuit of Sec. 4.1,
+// eq. (4)-(5):
+//   P1 = B^2,  P_i = L_i R_i  (i = 2, 3, 4),  L_i, R_i over {I, B, P1, ..., P_{i-1}},
+//   T15~ = I + g1 B + g2 P1 + g3 P2 + g4 P3 + P4.
+// App. B prints the 28 coefficients to three decimals only; composed exactly
+// those digits match 1/(1-z) through degree 14 only to ~3e-3, while Sec. 4.2
+// states a prefix error below 9e-7.  The library therefore moves the printed
+// point onto the prefix-exact solution set with a minimum-norm Gauss-Newton
+// iteration (x <- x - J^T (J J^T)^{-1} r, r_j = [T15~]_j - 1, j = 0..14) in
+// extended precision, with the Jacobian from forward-mode differentiation of
+// the circuit, and rounds the limit to double.  This runs once per process.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+namespace ns {
+namespace {
+
+typedef long double R;
+constexpr int NP = 28, NEQ = 15, DEG = 17;  // T15~ has degree 16
+
+// App. B, in the order L2[I,B,P1] R2[..] L3[I,B,P1,P2] R3[..]
+// L4[I,B,P1,P2,P3] R4[..] g1..g4.
+const double kPrinted[NP] = {
+    0.238, 0.241, 1.574,  0.048, -0.047, 0.889,
+    0.263, 0.919, 0.842, 0.819,  0.184, 0.068, 0.134, -1.405,
+    -0.005, -1.385, 0.022, 0.122, 0.275,  -0.701, 0.602, -0.624, -0.137, 0.328,
+    0.078, 1.778, 0.664, -0.024};
+
+struct Poly {
+  R c[DEG];
+  void zero() { for (int i = 0; i < DEG; ++i) c[i] = 0; }
+};
+struct DPoly {            // a polynomial and its derivative w.r.t. each coefficient
+  Poly v;
+  Poly d[NP];
+  void zero() { v.zero(); for (int p = 0; p < NP; ++p) d[p].zero(); }
+};
+
+void mul(const Poly& a, const Poly& b, Poly& out) {
+  Poly t; t.zero();
+  for (int i = 0; i < DEG; ++i)
+    if (a.c[i] != 0)
+      for (int j = 0; i + j < DEG; ++j) t.c[i + j] += a.c[i] * b.c[j];
+  out = t;
+}
+void axpy(R s, const Poly& x, Poly& y) { for (int i = 0; i < DEG; ++i) y.c[i] += s * x.c[i]; }
+
+// Evaluate the circuit at coefficients x: value of T15~ and d T15~ / d x_p.
+void circuit(const R* x, DPoly& T) {
+  static DPoly basis[6];
+  for (auto& b : basis) b.zero();
+  basis[0].v.c[0] = 1;               // I
+  basis[1].v.c[1] = 1;               // B
+  basis[2].v.c[2] = 1;               // P1 = B^2
+  int pos = 0;
+  for (int w = 3; w <= 5; ++w) {     // widths of the factors of P2, P3, P4
+    DPoly L, Rr;
+    L.zero(); Rr.zero();
+    for (int q = 0; q < w; ++q) {
+      const R cl = x[pos + q], cr = x[pos + w + q];
+      axpy(cl, basis[q].v, L.v);
+      axpy(cr, basis[q].v, Rr.v);
+      axpy(1, basis[q].v, L.d[pos + q]);
+      axpy(1, basis[q].v, Rr.d[pos + w + q]);
+      for (int p = 0; p < NP; ++p) {
+        axpy(cl, basis[q].d[p], L.d[p]);
+        axpy(cr, basis[q].d[p], Rr.d[p]);
+      }
+    }
+    DPoly& P = basis[w];
+    mul(L.v, Rr.v, P.v);
+    for (int p = 0; p < NP; ++p) {
+      Poly a, b;
+      mul(L.d[p], Rr.v, a);
+      mul(L.v, Rr.d[p], b);
+      for (int i = 0; i < DEG; ++i) P.d[p].c[i] = a.c[i] + b.c[i];
+    }
+    pos += 2 * w;
+  }
+  T.zero();
+  T.v.c[0] = 1;
+  for (int g = 0; g < 4; ++g) {      // g1 B + g2 P1 + g3 P2 + g4 P3
+    const R cg = x[24 + g];
+    const DPoly& b = basis[1 + g];
+    axpy(cg, b.v, T.v);
+    axpy(1, b.v, T.d[24 + g]);
+    for (int p = 0; p < NP; ++p) axpy(cg, b.d[p], T.d[p]);
+  }
+  axpy(1, basis[5].v, T.v);          // + P4
+  for (int p = 0; p < NP; ++p) axpy(1, basis[5].d[p], T.d[p]);
+}
+
+// Solve M y = r (NEQ x NEQ) by Gaussian elimination with partial pivoting.
+bool solve(R M[NEQ][NEQ], R* r) {
+  for (int c = 0; c < NEQ; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < NEQ; ++i)
+      if (fabsl(M[i][c]) > fabsl(M[piv][c])) piv = i;
+    if (M[piv][c] == 0) return false;
+    if (piv != c) {
+      for (int j = 0; j < NEQ; ++j) { R t = M[c][j]; M[c][j] = M[piv][j]; M[piv][j] = t; }
+      R t = r[c]; r[c] = r[piv]; r[piv] = t;
+    }
+    for (int i = c + 1; i < NEQ; ++i) {
+      const R f = M[i][c] / M[c][c];
+      for (int j = c; j < NEQ; ++j) M[i][j] -= f * M[c][j];
+      r[i] -= f * r[c];
+    }
+  }
+  for (int c = NEQ - 1; c >= 0; --c) {
+    R s = r[c];
+    for (int j = c + 1; j < NEQ; ++j) s -= M[c][j] * r[j];
+    r[c] = s / M[c][c];
+  }
+  return true;
+}
+
+struct Table {
+  double c[NP];
+  double prefix_err, spill15, spill16;
+  bool ok;
+};
+
+Table build() {
+  Table t{};
+  R x[NP];
+  for (int p = 0; p < NP; ++p) x[p] = kPrinted[p];
+  static DPoly T;
+  for (int it = 0; it < 30; ++it) {
+    circuit(x, T);
+    R r[NEQ], rmax = 0;
+    for (int j = 0; j < NEQ; ++j) {
+      r[j] = T.v.c[j] - 1;
+      rmax = fmaxl(rmax, fabsl(r[j]));
+    }
+    if (rmax < 1e-18L) break;
+    R M[NEQ][NEQ];
+    for (int a = 0; a < NEQ; ++a)
+      for (int b = 0; b < NEQ; ++b) {
+        R s = 0;
+        for (int p = 0; p < NP; ++p) s += T.d[p].c[a] * T.d[p].c[b];
+        M[a][b] = s;
+      }
+    if (!solve(M, r)) return t;
+    for (int p = 0; p < NP; ++p) {
+      R s = 0;
+      for (int j = 0; j < NEQ; ++j) s += T.d[p].c[j] * r[j];
+      x[p] -= s;
+    }
+  }
+  R xd[NP];
+  for (int p = 0; p < NP; ++p) {
+    t.c[p] = (double)x[p];
+    xd[p] = (R)t.c[p];
+  }
+  circuit(xd, T);  // the rounded doubles, in extended precision
+  R pe = 0;
+  for (int j = 0; j < NEQ; ++j) pe = fmaxl(pe, fabsl(T.v.c[j] - 1));
+  t.prefix_err = (double)pe;
+  t.spill15 = (double)T.v.c[15];
+  t.spill16 = (double)T.v.c[16];
+  t.ok = pe < 1e-12L;
+  return t;
+}
+
+}  // namespace
+
+// Returns the polished table (computed on first use).  ok = false if the
+// iteration failed, which would be a defect in this file.
+bool radix15_table(double c[28], double* prefix_err, double* s15, double* s16) {
+  static std::once_flag once;
+  static Table tab;
+  std::call_once(once, [] { tab = build(); });
+  std::memcpy(c, tab.c, sizeof(tab.c));
+  if (prefix_err) *prefix_err = tab.prefix_err;
+  if (s15) *s15 = tab.spill15;
+  if (s16) *s16 = tab.spill16;
+  return tab.ok;
+}
+
+}  // namespace ns

@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/ns.h declares, and its host-only logic (planning,
+product counts, radix-15 table, status strings, argument errors) agrees with
+the oracle and the paper."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, golden_rows
+from oracle import coeffs15, series
+
+LIB = os.path.join(ROOT, "paper_2602_11843_amd", "libns.so")
+
+
+@pytest.fixture(scope="module")
+def ns():
+    if not os.path.exists(LIB):
+        from paper_2602_11843_amd import build
+        build.build()
+    import paper_2602_11843_amd as ns
+    return ns
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "ns.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(ns_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("ns_eval", "ns_eval_ex", "ns_eval_batched", "ns_plan", "ns_create",
+                     "ns_destroy", "ns_status_string", "ns_workspace_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(ns):
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_abi(ns):
+    for name in _declared_functions():
+        if name in ("ns_create", "ns_destroy", "ns_last_error"):
+            continue
+        if name in ("ns_set_product_timing", "ns_product_timing"):
+            assert hasattr(ns.Handle, name)
+        else:
+            assert hasattr(ns, name), name
+
+
+METHOD_MAP = {"naive": "naive", "binary": "binary", "radix9": "radix9", "radix15": "radix15",
+              "radix9_resid": "radix9_resid", "quinary": "quinary", "ternary": "ternary",
+              "hensel": "hensel"}
+
+
+@pytest.mark.parametrize("method", list(METHOD_MAP))
+def test_plan_matches_oracle(ns, method):
+    for k in (1, 2, 3, 8, 9, 10, 80, 81, 82, 125, 225, 729, 3375, 4096, 6561, 10 ** 6):
+        assert ns.ns_plan(k, method) == series.plan(k, METHOD_MAP[method]), (method, k)
+
+
+def test_plan_reproduces_table2(ns):
+    cols = {"binary": 1, "quinary": 2, "radix9": 3, "radix15": 4}
+    for row in golden_rows("table2_counts.txt"):
+        for method, c in cols.items():
+            if row[c] != "-":
+                assert ns.ns_plan(int(row[0]), method)[2] == int(row[c])
+
+
+def test_plan_errors(ns):
+    with pytest.raises(ns.NSError) as e:
+        ns.ns_plan(0, "radix9")
+    assert e.value.status == -1
+    with pytest.raises(ns.NSError) as e:
+        ns.ns_plan(10, 99)
+    assert e.value.status == -1
+    with pytest.raises(ns.NSError) as e:           # k_eff = 15^17 overflows int64
+        ns.ns_plan(2 ** 63 - 1, "radix15")
+    assert e.value.status == -5
+
+
+def test_radix15_table_agrees_with_oracle(ns):
+    """The library derives its table with its own Gauss-Newton (C++, long
+    double); it must land on the oracle's polished doubles."""
+    c, pe, s15, s16 = ns.ns_radix15_coeffs()
+    ref = coeffs15.polished()
+    for a, b in zip(c, ref):
+        assert abs(a - b) <= 4 * abs(b) * 2.0 ** -52
+    assert pe < 1e-15
+    assert round(s15, 3) == 0.185 and round(s16, 3) == 0.458
+
+
+def test_workspace_bytes(ns):
+    b9 = ns.ns_workspace_bytes(4096, "radix9", "f64")
+    assert b9 >= 9 * 4096 * 4096 * 8
+    assert ns.ns_workspace_bytes(4096, "radix9", "f32") < b9
+    with pytest.raises(ns.NSError):
+        ns.ns_workspace_bytes(0, "radix9", "f64")
+
+
+def test_status_strings(ns):
+    assert ns.ns_status_string(0) == "ok"
+    assert "argument" in ns.ns_status_string(-1)
+    assert ns.ns_status_string(-4).startswith("HIP")
