@@ -52,8 +52,10 @@ struct GemmParams {
 // multiple of it).  Small n use smaller tiles.
 int engine_tile(Engine e, int n);
 
-// Launch one product on `stream`.  Returns hipSuccess or the launch error.
-hipError_t launch_gemm(Engine e, const GemmParams& p, hipStream_t stream);
+// Launch one product on `stream`.  `host` is the parameter block on the host
+// (for the grid), `dev` the same block already in device memory (the kernel
+// reads the epilogue part from there).  Returns hipSuccess or the launch error.
+hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t stream);
 
 // Elementwise helpers (util.hip).
 // dst (padded n_pad x n_pad, ld n_pad) <- src (n x n, lda) converted; the

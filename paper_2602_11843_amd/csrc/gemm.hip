@@ -50,41 +50,89 @@ struct EpiState {
   int bad;
 };
 
-__device__ __forceinline__ void epi_element(const GemmParams& p, int row, int col, double v,
-                                            EpiState& st) {
+// Load / store VEC consecutive elements of a row-major matrix at idx as
+// doubles; `f64` selects the element type.  idx is a multiple of VEC, so the
+// accesses are 8-, 16- or 32-byte aligned vectors.
+template <int VEC>
+__device__ __forceinline__ void load_vec(const void* p, int f64, size_t idx, double (&v)[VEC]) {
+  if (f64) {
+    const double2* q = reinterpret_cast<const double2*>(static_cast<const double*>(p) + idx);
+#pragma unroll
+    for (int i = 0; i < VEC / 2; ++i) {
+      const double2 t = q[i];
+      v[2 * i] = t.x;
+      v[2 * i + 1] = t.y;
+    }
+  } else {
+    if constexpr (VEC == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(static_cast<const float*>(p) + idx);
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+      const float2 t = *reinterpret_cast<const float2*>(static_cast<const float*>(p) + idx);
+      v[0] = t.x; v[1] = t.y;
+    }
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void store_vec(void* p, int f64, size_t idx, double (&v)[VEC]) {
+  if (f64) {
+    double2* q = reinterpret_cast<double2*>(static_cast<double*>(p) + idx);
+#pragma unroll
+    for (int i = 0; i < VEC / 2; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+  } else {
+    if constexpr (VEC == 4) {
+      *reinterpret_cast<float4*>(static_cast<float*>(p) + idx) =
+          make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    } else {
+      *reinterpret_cast<float2*>(static_cast<float*>(p) + idx) = make_float2((float)v[0], (float)v[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) v[i] = (double)(float)v[i];   // the value actually stored
+  }
+}
+
+// Apply the affine epilogue to VEC consecutive product values c[] at
+// (row, col .. col + VEC - 1).  Every loop has a compile-time trip count so
+// the kernel-argument struct is only ever indexed statically.
+template <int VEC>
+__device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, const double (&c)[VEC],
+                                        EpiState& st) {
   const size_t idx = (size_t)row * p.ld + col;
-  double z[kMaxZ];
+  double z[kMaxZ][VEC];
 #pragma unroll
   for (int i = 0; i < kMaxZ; ++i) {
-    z[i] = 0.0;
-    if (i < p.nz)
-      z[i] = p.zf64[i] ? static_cast<const double*>(p.Z[i])[idx]
-                       : (double)static_cast<const float*>(p.Z[i])[idx];
-  }
-  const double idv = (row == col) ? 1.0 : 0.0;
-  for (int o = 0; o < p.no; ++o) {
-    const EpiOut& e = p.out[o];
-    double y = e.a * v + e.id * idv;
+    if (i < p.nz) load_vec<VEC>(p.Z[i], p.zf64[i], idx, z[i]);
+    else
 #pragma unroll
-    for (int i = 0; i < kMaxZ; ++i) y += e.z[i] * z[i];
-    if (e.f64) {
-      static_cast<double*>(e.ptr)[idx] = y;
-    } else {
-      const float yf = (float)y;
-      static_cast<float*>(e.ptr)[idx] = yf;
-      y = (double)yf;
+      for (int e = 0; e < VEC; ++e) z[i][e] = 0.0;
+  }
+#pragma unroll
+  for (int o = 0; o < kMaxOut; ++o) {
+    if (o >= p.no) break;
+    const EpiOut& e = p.out[o];
+    double y[VEC];
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) {
+      y[t] = e.a * c[t] + ((row == col + t) ? e.id : 0.0);
+#pragma unroll
+      for (int i = 0; i < kMaxZ; ++i) y[t] += e.z[i] * z[i][t];
     }
+    store_vec<VEC>(e.ptr, e.f64, idx, y);
     if (o == 0) {
-      st.ssq += y * y;
-      if (!isfinite(y)) st.bad = 1;
-      st.amax = fmaxf(st.amax, (float)fabs(y));
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) {
+        st.ssq += y[t] * y[t];
+        if (!isfinite(y[t])) st.bad = 1;
+        st.amax = fmaxf(st.amax, (float)fabs(y[t]));
+      }
     }
   }
 }
 
 // Reduce the per-thread statistics over the workgroup and publish them with
-// one atomic each.  `scratch` is LDS of at least 3 * (THREADS / 64) words
-// (the tile buffers are reused; the caller synchronises before the call).
+// one atomic each.  `scratch` is LDS of at least 3 * (THREADS / 64) doubles;
+// the caller synchronises before the call.
 template <int THREADS>
 __device__ __forceinline__ void publish_stats(const GemmParams& p, EpiState st, double* scratch) {
   if (!p.sumsq && !p.nonfinite && !p.amax) return;
@@ -156,8 +204,11 @@ struct PolF64 {
       for (int j = 0; j < NJ; ++j)
         acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i], bf[j], acc.v[i][j], 0, 0, 0);
   }
-  template <class F>
-  static __device__ __forceinline__ void epilogue(Acc& acc, int lane, int wm, int wn, F&& f) {
+  // Sum the four k-slices (lanes differing in bits 2-3), then write this
+  // wave's WTM x WTN results into the staging tile C (row pitch CPITCH, rows
+  // relative to the wave's first row).
+  using CT = double;
+  static __device__ __forceinline__ void stage(Acc& acc, int lane, int wn, CT* C, int cpitch) {
     const int i = lane >> 4, b = (lane >> 2) & 3, j = lane & 3;
 #pragma unroll
     for (int a = 0; a < NI; ++a)
@@ -168,13 +219,13 @@ struct PolF64 {
         x += __shfl_xor(x, 8);
         acc.v[a][c] = x;
       }
-    // after the reduction the four block-lanes hold the same sums; block-lane
-    // b stores the fragments whose index is b mod 4
+    // the four block-lanes now hold the same sums; block-lane b writes the
+    // fragments whose index is b mod 4
 #pragma unroll
     for (int a = 0; a < NI; ++a)
 #pragma unroll
       for (int c = 0; c < NJ; ++c)
-        if (((a * NJ + c) & 3) == b) f(wm * WTM + 4 * a + i, wn * WTN + 4 * c + j, acc.v[a][c]);
+        if (((a * NJ + c) & 3) == b) C[(4 * a + i) * cpitch + wn * WTN + 4 * c + j] = acc.v[a][c];
   }
 };
 
@@ -222,8 +273,8 @@ struct PolF32 {
           acc.v[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j], acc.v[i][j], 0, 0, 0);
     }
   }
-  template <class F>
-  static __device__ __forceinline__ void epilogue(Acc& acc, int lane, int wm, int wn, F&& f) {
+  using CT = float;
+  static __device__ __forceinline__ void stage(Acc& acc, int lane, int wn, CT* C, int cpitch) {
     const int q = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int a = 0; a < NI; ++a)
@@ -231,93 +282,131 @@ struct PolF32 {
       for (int c = 0; c < NJ; ++c)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          f(wm * WTM + 16 * a + 4 * g + r, wn * WTN + 16 * c + q, (double)acc.v[a][c][r]);
+          C[(16 * a + 4 * g + r) * cpitch + wn * WTN + 16 * c + q] = acc.v[a][c][r];
   }
 };
 
 // ---------------------------------------------------------------------------
 // the product kernel (shared by the FP64 and FP32 policies)
 // ---------------------------------------------------------------------------
-template <class P>
-struct Loader {
-  using T = typename P::T;
-  static constexpr int EPV = 16 / sizeof(T);                 // elements per 16-byte vector
-  static constexpr int A_VPR = P::BK / EPV, A_VEC = P::BM * A_VPR;
-  static constexpr int B_VPR = P::BN / EPV, B_VEC = P::BK * B_VPR;
-  static constexpr int NA = (A_VEC + P::THREADS - 1) / P::THREADS;
-  static constexpr int NB = (B_VEC + P::THREADS - 1) / P::THREADS;
-  static_assert(A_VEC % P::THREADS == 0 && B_VEC % P::THREADS == 0, "tile not divisible");
-  uint4 ra[NA], rb[NB];
-  __device__ __forceinline__ void load(const T* __restrict__ X, const T* __restrict__ Y, int ld,
-                                       int row0, int col0, int k0, int tid) {
-#pragma unroll
-    for (int it = 0; it < NA; ++it) {
-      const int v = tid + it * P::THREADS, r = v / A_VPR, c = v % A_VPR;
-      ra[it] = *reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * ld + k0 + c * EPV);
-    }
-#pragma unroll
-    for (int it = 0; it < NB; ++it) {
-      const int v = tid + it * P::THREADS, r = v / B_VPR, c = v % B_VPR;
-      rb[it] = *reinterpret_cast<const uint4*>(Y + (size_t)(k0 + r) * ld + col0 + c * EPV);
-    }
-  }
-  __device__ __forceinline__ void store(T* As, T* Bs, int tid) {
-#pragma unroll
-    for (int it = 0; it < NA; ++it) {
-      const int v = tid + it * P::THREADS, r = v / A_VPR, c = v % A_VPR;
-      *reinterpret_cast<uint4*>(&As[r * P::APITCH + c * EPV]) = ra[it];
-    }
-#pragma unroll
-    for (int it = 0; it < NB; ++it) {
-      const int v = tid + it * P::THREADS, r = v / B_VPR, c = v % B_VPR;
-      *reinterpret_cast<uint4*>(&Bs[r * P::BPITCH + c * EPV]) = rb[it];
-    }
-  }
+// The kernel's own arguments are only what the k-loop needs; the epilogue
+// parameters are read from device memory after the loop, so they occupy no
+// registers while the matrix cores run.
+struct MainArgs {
+  const void* X;
+  const void* Y;
+  int n;
+  int ld;
+  const GemmParams* epi;
 };
 
 template <class P>
-__global__ __launch_bounds__(P::THREADS) void gemm_kernel(const GemmParams p) {
+__global__ __launch_bounds__(P::THREADS) void gemm_kernel(const MainArgs args) {
   using T = typename P::T;
+  using CT = typename P::CT;
   constexpr int A_SZ = P::BM * P::APITCH, B_SZ = P::BK * P::BPITCH;
-  __shared__ __align__(16) T smem[2 * (A_SZ + B_SZ)];
+  constexpr int CPITCH = P::BN + 16 / (int)sizeof(CT);
+  constexpr int STAGE_ELEMS = (P::WTM * CPITCH * (int)sizeof(CT) + (int)sizeof(T) - 1) / (int)sizeof(T);
+  constexpr int SMEM_ELEMS = 2 * (A_SZ + B_SZ) > STAGE_ELEMS ? 2 * (A_SZ + B_SZ) : STAGE_ELEMS;
+  __shared__ __align__(16) T smem[SMEM_ELEMS];
   // buffer b: A tile at smem + b * A_SZ, B tile at smem + 2 * A_SZ + b * B_SZ
 
-  const int tiles_m = p.n / P::BM, tiles_n = p.n / P::BN;
+  constexpr int EPV = 16 / sizeof(T);                        // elements per 16-byte vector
+  constexpr int A_VPR = P::BK / EPV, A_VEC = P::BM * A_VPR;  // vectors per row / per tile
+  constexpr int B_VPR = P::BN / EPV, B_VEC = P::BK * B_VPR;
+  constexpr int NA = A_VEC / P::THREADS, NB = B_VEC / P::THREADS;
+  static_assert(A_VEC % P::THREADS == 0 && B_VEC % P::THREADS == 0, "tile not divisible");
+
+  const int n = args.n, ld = args.ld;
+  const int tiles_m = n / P::BM, tiles_n = n / P::BN;
   int tm, tn;
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
   const int row0 = tm * P::BM, col0 = tn * P::BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / P::NWN, wn = wave % P::NWN;
-  const T* X = static_cast<const T*>(p.X);
-  const T* Y = static_cast<const T*>(p.Y);
+
+  // per-thread global offsets and LDS offsets of its 16-byte vectors
+  const T* __restrict__ Xp = static_cast<const T*>(args.X);
+  const T* __restrict__ Yp = static_cast<const T*>(args.Y);
+  size_t ga[NA], gb[NB];
+  int sa[NA], sb[NB];
+#pragma unroll
+  for (int it = 0; it < NA; ++it) {
+    const int v = tid + it * P::THREADS, r = v / A_VPR, c = v % A_VPR;
+    ga[it] = (size_t)(row0 + r) * ld + c * EPV;
+    sa[it] = r * P::APITCH + c * EPV;
+  }
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int v = tid + it * P::THREADS, r = v / B_VPR, c = v % B_VPR;
+    gb[it] = (size_t)r * ld + col0 + c * EPV;
+    sb[it] = r * P::BPITCH + c * EPV;
+  }
+  uint4 ra[NA], rb[NB];
 
   typename P::Acc acc;
   P::zero(acc);
-  Loader<P> ld;
-  const int nk = p.n / P::BK;
-  ld.load(X, Y, p.ld, row0, col0, 0, tid);
-  ld.store(smem, smem + 2 * A_SZ, tid);
+  const int nk = n / P::BK;
+#pragma unroll
+  for (int it = 0; it < NA; ++it) ra[it] = *reinterpret_cast<const uint4*>(Xp + ga[it]);
+#pragma unroll
+  for (int it = 0; it < NB; ++it) rb[it] = *reinterpret_cast<const uint4*>(Yp + gb[it]);
+#pragma unroll
+  for (int it = 0; it < NA; ++it) *reinterpret_cast<uint4*>(smem + sa[it]) = ra[it];
+#pragma unroll
+  for (int it = 0; it < NB; ++it) *reinterpret_cast<uint4*>(smem + 2 * A_SZ + sb[it]) = rb[it];
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     const int cur = kc & 1;
-    const bool more = kc + 1 < nk;
-    if (more) ld.load(X, Y, p.ld, row0, col0, (kc + 1) * P::BK, tid);
+    // prefetch the next chunk (the last iteration re-reads its own chunk into
+    // the idle buffer, which nothing reads afterwards: no branch, so the
+    // prefetch registers stay in registers across the matrix-core work)
+    const size_t ka = (size_t)min(kc + 1, nk - 1) * P::BK, kb = ka * ld;
+#pragma unroll
+    for (int it = 0; it < NA; ++it) ra[it] = *reinterpret_cast<const uint4*>(Xp + ga[it] + ka);
+#pragma unroll
+    for (int it = 0; it < NB; ++it) rb[it] = *reinterpret_cast<const uint4*>(Yp + gb[it] + kb);
     P::chunk(smem + cur * A_SZ, smem + 2 * A_SZ + cur * B_SZ, acc, wm, wn, lane);
-    if (more) ld.store(smem + (cur ^ 1) * A_SZ, smem + 2 * A_SZ + (cur ^ 1) * B_SZ, tid);
+    T* As = smem + (cur ^ 1) * A_SZ;
+    T* Bs = smem + 2 * A_SZ + (cur ^ 1) * B_SZ;
+#pragma unroll
+    for (int it = 0; it < NA; ++it) *reinterpret_cast<uint4*>(As + sa[it]) = ra[it];
+#pragma unroll
+    for (int it = 0; it < NB; ++it) *reinterpret_cast<uint4*>(Bs + sb[it]) = rb[it];
     __syncthreads();
   }
 
+  // Epilogue in NWM passes: the waves of wave-row `pass` stage their WTM x BN
+  // results in LDS, then the whole workgroup applies the affine outputs to
+  // those rows with row-contiguous 16-byte vectors (coalesced Z reads and
+  // output writes).  The last loop barrier makes smem free for reuse.
+  const GemmParams& p = *args.epi;
+  constexpr int VEC = 16 / (int)sizeof(CT);          // 2 doubles or 4 floats
+  constexpr int VPR = P::BN / VEC;                   // vectors per row
+  CT* C = reinterpret_cast<CT*>(smem);
   EpiState st{0.0, 0.f, 0};
-  P::epilogue(acc, lane, wm, wn,
-              [&](int r, int c, double v) { epi_element(p, row0 + r, col0 + c, v, st); });
+#pragma unroll 1
+  for (int pass = 0; pass < P::NWM; ++pass) {
+    if (wm == pass) P::stage(acc, lane, wn, C, CPITCH);
+    __syncthreads();
+    for (int v = tid; v < P::WTM * VPR; v += P::THREADS) {
+      const int r = v / VPR, cv = (v % VPR) * VEC;
+      double c[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
+      epi_vec<VEC>(p, row0 + pass * P::WTM + r, col0 + cv, c, st);
+    }
+    __syncthreads();
+  }
   publish_stats<P::THREADS>(p, st, reinterpret_cast<double*>(smem));
 }
 
 template <class P>
-hipError_t launch(const GemmParams& p, hipStream_t s) {
-  if (p.n % P::BM || p.n % P::BN || p.n % P::BK) return hipErrorInvalidValue;
-  const int grid = (p.n / P::BM) * (p.n / P::BN);
-  hipLaunchKernelGGL(gemm_kernel<P>, dim3(grid), dim3(P::THREADS), 0, s, p);
+hipError_t launch(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
+  if (host.n % P::BM || host.n % P::BN || host.n % P::BK) return hipErrorInvalidValue;
+  const int grid = (host.n / P::BM) * (host.n / P::BN);
+  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
+  hipLaunchKernelGGL(gemm_kernel<P>, dim3(grid), dim3(P::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -331,7 +420,8 @@ constexpr int kBigMin = 2048;          // n from which the large tiles are used
 
 }  // namespace
 
-hipError_t launch_gemm_lowp(Engine e, const GemmParams& p, hipStream_t s);  // gemm_lowp.hip
+hipError_t launch_gemm_lowp(Engine e, const GemmParams& host, const GemmParams* dev,
+                            hipStream_t s);  // gemm_lowp.hip
 int engine_tile_lowp(Engine e, int n);
 
 int engine_tile(Engine e, int n) {
@@ -342,11 +432,11 @@ int engine_tile(Engine e, int n) {
   }
 }
 
-hipError_t launch_gemm(Engine e, const GemmParams& p, hipStream_t s) {
+hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s) {
   switch (e) {
-    case ENG_F64: return p.n >= kBigMin ? launch<F64Big>(p, s) : launch<F64Small>(p, s);
-    case ENG_F32: return p.n >= kBigMin ? launch<F32Big>(p, s) : launch<F32Small>(p, s);
-    default: return launch_gemm_lowp(e, p, s);
+    case ENG_F64: return host.n >= kBigMin ? launch<F64Big>(host, dev, s) : launch<F64Small>(host, dev, s);
+    case ENG_F32: return host.n >= kBigMin ? launch<F32Big>(host, dev, s) : launch<F32Small>(host, dev, s);
+    default: return launch_gemm_lowp(e, host, dev, s);
   }
 }
 

@@ -5,6 +5,8 @@ namespace ns {
 
 int engine_tile_lowp(Engine, int) { return 128; }
 
-hipError_t launch_gemm_lowp(Engine, const GemmParams&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_gemm_lowp(Engine, const GemmParams&, const GemmParams*, hipStream_t) {
+  return hipErrorNotSupported;
+}
 
 }  // namespace ns

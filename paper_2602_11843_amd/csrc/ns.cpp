@@ -76,6 +76,15 @@ struct ns_handle {
   std::vector<hipEvent_t> ev;    // pairs (start, stop)
   size_t ev_used = 0;
   double flops_logged = 0.0;
+  // product parameter blocks: staged in pinned host memory, uploaded with one
+  // copy per call; `params_free` marks when the staging buffer may be reused
+  ns::GemmParams* params_host = nullptr;
+  ns::GemmParams* params_dev = nullptr;
+  size_t params_cap = 0;
+  hipEvent_t params_free = nullptr;
+  // recorded after each call's last operation; the next call's stream waits on
+  // it, so calls on different streams never share the workspace concurrently
+  hipEvent_t call_done = nullptr;
   // batched state (owned by batched.hip)
   void* batched = nullptr;
 };
@@ -212,6 +221,16 @@ struct Out {
   double id;
 };
 
+// A recorded device operation of a schedule.
+struct Op {
+  enum Kind { GEMM, IDENTITY, AMAX } kind;
+  Engine e;
+  GemmParams p;      // GEMM
+  void* ptr;         // IDENTITY / AMAX target
+  int f64;
+  unsigned* amax;
+};
+
 struct Ctx {
   ns_handle* h;
   hipStream_t s;
@@ -225,6 +244,7 @@ struct Ctx {
   int status = NS_OK;
   char* arena;
   size_t arena_off = 0;
+  std::vector<Op> ops;
 
   Buf take(int f64) {
     Buf b;
@@ -235,12 +255,41 @@ struct Ctx {
     return b;
   }
 
-  // C = X Y on engine e; Z inputs; outputs as affine combinations of
+  unsigned* new_amax_slot() {
+    if (next_amax >= kAmaxSlots) {
+      status = fail(NS_ERR_RANGE, "too many products for the max-abs slots");
+      return nullptr;
+    }
+    return &scal->amax[next_amax++];
+  }
+
+  void identity(const Buf& b) {
+    Op op{};
+    op.kind = Op::IDENTITY;
+    op.ptr = b.p;
+    op.f64 = b.f64;
+    ops.push_back(op);
+  }
+
+  void amax(Buf& b) {
+    b.amax = new_amax_slot();
+    if (!b.amax || b.f64) return;
+    Op op{};
+    op.kind = Op::AMAX;
+    op.ptr = b.p;
+    op.amax = b.amax;
+    ops.push_back(op);
+  }
+
+  // Record C = X Y on engine e; Z inputs; outputs as affine combinations of
   // (C, Z..., I).  norm_level >= 0 accumulates ||output 0||_F^2 there.
   void gemm(Engine e, const Buf& X, const Buf& Y, std::initializer_list<Buf> Z,
             std::initializer_list<Out> outs, int norm_level = -1) {
     if (status != NS_OK) return;
-    GemmParams p{};
+    Op op{};
+    op.kind = Op::GEMM;
+    op.e = e;
+    GemmParams& p = op.p;
     p.X = X.p;
     p.Y = Y.p;
     p.n = np;
@@ -263,60 +312,88 @@ struct Ctx {
     p.sumsq = norm_level >= 0 ? &scal->level_sumsq[norm_level] : nullptr;
     p.nonfinite = &scal->nonfinite;
     if (eng == ENG_F16S) {
-      // the scaled-FP16 engine needs each operand's max-abs: output 0 records it
-      if (next_amax >= kAmaxSlots) {
-        status = fail(NS_ERR_RANGE, "too many products for the max-abs slots");
-        return;
-      }
-      p.amax = &scal->amax[next_amax++];
+      // the scaled-FP16 engine needs each operand's max-abs: the epilogue
+      // records it for output 0, a separate pass for the other outputs
+      p.amax = new_amax_slot();
       p.xamax = X.amax;
       p.yamax = Y.amax;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (h->timing) {
-      if (h->ev_used + 2 > h->ev.size()) {
-        for (int i = 0; i < 64; ++i) {
-          hipEvent_t ev;
-          if (hipEventCreate(&ev) != hipSuccess) {
-            status = fail(NS_ERR_HIP, "hipEventCreate failed");
-            return;
-          }
-          h->ev.push_back(ev);
-        }
-      }
-      e0 = h->ev[h->ev_used];
-      e1 = h->ev[h->ev_used + 1];
-      h->ev_used += 2;
-      hipEventRecord(e0, s);
-    }
-    const hipError_t err = launch_gemm(e, p, s);
-    if (h->timing) {
-      hipEventRecord(e1, s);
-      h->flops_logged += 2.0 * (double)n * n * n;
-    }
-    if (err != hipSuccess) {
-      status = fail(NS_ERR_HIP, "product launch failed: %s", hipGetErrorString(err));
-      return;
-    }
+    ops.push_back(op);
     ++gemms;
     if (p.amax) {
-      // every output of this product is a combination whose magnitude the
-      // epilogue bounds only for output 0; the remaining outputs get their own
-      // max-abs pass right away (they are the next products' operands)
-      for (size_t i = 0; i < outs.size(); ++i) {
-        Buf* b = (outs.begin() + i)->b;
-        if (i == 0) {
-          b->amax = p.amax;
-        } else {
-          if (next_amax >= kAmaxSlots) {
-            status = fail(NS_ERR_RANGE, "too many max-abs slots");
-            return;
-          }
-          b->amax = &scal->amax[next_amax++];
-          if (!b->f64) launch_amax(static_cast<const float*>(b->p), (size_t)np * np, b->amax, s);
-        }
+      size_t i = 0;
+      for (const Out& o : outs) {
+        if (i++ == 0) o.b->amax = p.amax;
+        else amax(*o.b);
       }
     }
+  }
+
+  // Upload every recorded parameter block with one copy, then launch the
+  // recorded operations in order on the stream.
+  int execute() {
+    if (status != NS_OK) return status;
+    size_t ng = 0;
+    for (const Op& op : ops) ng += op.kind == Op::GEMM;
+    if (ng > h->params_cap) {
+      NS_HIP(hipDeviceSynchronize());   // earlier kernels may still read the old blocks
+      if (h->params_host) NS_HIP(hipHostFree(h->params_host));
+      if (h->params_dev) NS_HIP(hipFree(h->params_dev));
+      h->params_host = nullptr;
+      h->params_dev = nullptr;
+      h->params_cap = 0;
+      const size_t cap = std::max<size_t>(ng, 256);
+      if (hipHostMalloc((void**)&h->params_host, cap * sizeof(GemmParams)) != hipSuccess ||
+          hipMalloc((void**)&h->params_dev, cap * sizeof(GemmParams)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(NS_ERR_NOMEM, "parameter buffers (%zu blocks) could not be allocated", cap);
+      }
+      h->params_cap = cap;
+    }
+    if (!h->params_free) NS_HIP(hipEventCreateWithFlags(&h->params_free, hipEventDisableTiming));
+    NS_HIP(hipEventSynchronize(h->params_free));    // the previous call's upload has finished
+    size_t gi = 0;
+    for (const Op& op : ops)
+      if (op.kind == Op::GEMM) h->params_host[gi++] = op.p;
+    if (ng) {
+      NS_HIP(hipMemcpyAsync(h->params_dev, h->params_host, ng * sizeof(GemmParams),
+                            hipMemcpyHostToDevice, s));
+      NS_HIP(hipEventRecord(h->params_free, s));
+    }
+    gi = 0;
+    for (const Op& op : ops) {
+      if (op.kind == Op::IDENTITY) {
+        NS_HIP(launch_set_identity(op.ptr, op.f64, np, s));
+        continue;
+      }
+      if (op.kind == Op::AMAX) {
+        NS_HIP(launch_amax(static_cast<const float*>(op.ptr), (size_t)np * np, op.amax, s));
+        continue;
+      }
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (h->timing) {
+        if (h->ev_used + 2 > h->ev.size()) {
+          for (int i = 0; i < 64; ++i) {
+            hipEvent_t ev;
+            NS_HIP(hipEventCreate(&ev));
+            h->ev.push_back(ev);
+          }
+        }
+        e0 = h->ev[h->ev_used];
+        e1 = h->ev[h->ev_used + 1];
+        h->ev_used += 2;
+        NS_HIP(hipEventRecord(e0, s));
+      }
+      const hipError_t err = launch_gemm(op.e, op.p, h->params_dev + gi, s);
+      ++gi;
+      if (err != hipSuccess) return fail(NS_ERR_HIP, "product launch failed: %s", hipGetErrorString(err));
+      if (h->timing) {
+        NS_HIP(hipEventRecord(e1, s));
+        h->flops_logged += 2.0 * (double)n * n * n;
+      }
+    }
+    ops.clear();
+    return NS_OK;
   }
 };
 
@@ -387,7 +464,7 @@ int run_schedule(Ctx& c, int method, int levels, const Buf& Ain_w, const Buf* Ai
   switch (method) {
     case NS_NAIVE: {                                   // S <- I + A S
       Buf S = c.take(W64), S2 = c.take(W64);
-      launch_set_identity(S.p, W64, c.np, c.s);
+      c.identity(S);
       for (int i = 0; i < levels; ++i) {
         c.gemm(c.eng, A, S, {}, {o(S2, 1.0, 0, 0, 0, 1.0)});
         std::swap(S, S2);
@@ -403,9 +480,9 @@ int run_schedule(Ctx& c, int method, int levels, const Buf& Ain_w, const Buf* Ai
       Buf S64;
       if (c.mixed) {
         S64 = c.take(1);
-        launch_set_identity(S64.p, 1, c.np, c.s);
+        c.identity(S64);
       }
-      launch_set_identity(S.p, W64, c.np, c.s);
+      c.identity(S);
       Buf U, X1, P, Q, T;
       if (method == NS_RADIX9) { U = c.take(W64); X1 = c.take(W64); P = c.take(W64); Q = c.take(W64); T = c.take(W64); }
       if (method == NS_QUINARY) { U = c.take(W64); X1 = c.take(W64); T = c.take(W64); }
@@ -442,10 +519,10 @@ int run_schedule(Ctx& c, int method, int levels, const Buf& Ain_w, const Buf* Ai
       // Y_0 = I, R_0 = A;  Y <- Y f(R);  R <- I - (I - A) Y   (eq. (8))
       Buf Y = c.take(W64), Y2 = c.take(W64), R = c.take(W64);
       Buf Y64, A64;
-      launch_set_identity(Y.p, W64, c.np, c.s);
+      c.identity(Y);
       if (c.mixed) {
         Y64 = c.take(1);
-        launch_set_identity(Y64.p, 1, c.np, c.s);
+        c.identity(Y64);
         A64 = *Ain64;
       }
       // R_0 = A: the first level reads the copy of A directly
@@ -529,6 +606,8 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   if ((st = plan(k, method, &k_eff, &levels, &gemms_formula))) return st;
   NS_HIP(hipSetDevice(h->device));
   if ((st = ensure_workspace(h, workspace_bytes(n, method, dtype)))) return st;
+  if (!h->call_done) NS_HIP(hipEventCreateWithFlags(&h->call_done, hipEventDisableTiming));
+  else NS_HIP(hipStreamWaitEvent(s, h->call_done, 0));
 
   Ctx c{};
   c.h = h;
@@ -550,14 +629,13 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
     A64 = c.take(1);
     NS_HIP(launch_pad_copy(A, 1, n, lda, A64.p, 1, c.np, s));
   }
-  if (c.eng == ENG_F16S) {
-    Aw.amax = &c.scal->amax[c.next_amax++];
-    NS_HIP(launch_amax(static_cast<const float*>(Aw.p), (size_t)c.np * c.np, Aw.amax, s));
-  }
+  if (c.eng == ENG_F16S) c.amax(Aw);
   Result res;
   if ((st = run_schedule(c, method, levels, Aw, c.mixed ? &A64 : nullptr, &res))) return st;
+  if ((st = c.execute())) return st;
   const int out64 = in64;
   NS_HIP(launch_unpad_copy(res.S.p, res.S.f64, c.np, out, out64, n, ldo, s));
+  NS_HIP(hipEventRecord(h->call_done, s));
 
   if (rep) {
     Scalars hs;
@@ -608,6 +686,10 @@ int ns_destroy(ns_handle* h) {
   (void)hipDeviceSynchronize();
   ns::batched_release(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->params_free) (void)hipEventDestroy(h->params_free);
+  if (h->call_done) (void)hipEventDestroy(h->call_done);
+  if (h->params_host) (void)hipHostFree(h->params_host);
+  if (h->params_dev) (void)hipFree(h->params_dev);
   if (h->ws) (void)hipFree(h->ws);
   delete h;
   return NS_OK;
