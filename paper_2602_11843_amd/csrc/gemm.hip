@@ -169,18 +169,25 @@ __device__ __forceinline__ void publish_stats(const GemmParams& p, EpiState st, 
 //   A operand  A_b[i][k], i = l&3,  k = l>>4
 //   B operand  B_b[k][j], j = l&3,  k = l>>4
 //   result     D_b[i][j], i = l>>4, j = l&3
-// (decoded on the device).  Block b takes k-slice 4b..4b+3 of a 16-wide
-// k-chunk, so one instruction advances a 4x4 output fragment by 16 k.
+// (decoded on the device).  The four blocks take four disjoint k-slices, so
+// one instruction advances a 4x4 output fragment by 16 k; the block partial
+// sums are added across lanes once per tile.
 // ---------------------------------------------------------------------------
-template <int NWM_, int NWN_, int NI_, int NJ_>
+template <int NWM_, int NWN_, int NI_, int NJ_, int KS_>
 struct PolF64 {
   using T = double;
   static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
+  static constexpr int KS = KS_;           // instructions per fragment pair per chunk
   static constexpr int WTM = 4 * NI, WTN = 4 * NJ;
-  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16;
+  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16 * KS;
   static constexpr int THREADS = 64 * NWM * NWN;
-  static constexpr int APITCH = BK;       // fragment reads are one contiguous 512 B run
-  static constexpr int BPITCH = BN + 4;   // 16 k-rows of a fragment spread over banks
+  // Lane slot kk = 4 b + k (0..15) owns chunk columns KS*kk .. KS*kk + KS - 1,
+  // one per instruction step s: its A values for all steps are one
+  // contiguous KS-double read, and the A reads of a wave cover 4 full rows.
+  static constexpr int APITCH = BK;
+  // B reads touch 16 rows KS apart; a pitch of BN + 2 doubles puts rows
+  // 2 apart 32 bytes apart in the banks (at most 2-way conflicts).
+  static constexpr int BPITCH = BN + 2;
   struct Acc {
     double v[NI][NJ];
   };
@@ -193,16 +200,33 @@ struct PolF64 {
   static __device__ __forceinline__ void chunk(const T* __restrict__ As, const T* __restrict__ Bs,
                                                Acc& acc, int wm, int wn, int lane) {
     const int q = lane & 3, kk = 4 * ((lane >> 2) & 3) + (lane >> 4);
-    double af[NI], bf[NJ];
+    double af[NI][KS];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) af[i] = As[(wm * WTM + 4 * i + q) * APITCH + kk];
+    for (int i = 0; i < NI; ++i) {
+      const double* src = &As[(wm * WTM + 4 * i + q) * APITCH + KS * kk];
+      if constexpr (KS % 2 == 0) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) bf[j] = Bs[kk * BPITCH + wn * WTN + 4 * j + q];
+        for (int s = 0; s < KS; s += 2) {
+          const double2 t = *reinterpret_cast<const double2*>(src + s);
+          af[i][s] = t.x;
+          af[i][s + 1] = t.y;
+        }
+      } else {
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+        for (int s = 0; s < KS; ++s) af[i][s] = src[s];
+      }
+    }
 #pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i], bf[j], acc.v[i][j], 0, 0, 0);
+    for (int s = 0; s < KS; ++s) {
+      double bf[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) bf[j] = Bs[(KS * kk + s) * BPITCH + wn * WTN + 4 * j + q];
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf[j], acc.v[i][j], 0, 0, 0);
+    }
   }
   // Sum the four k-slices (lanes differing in bits 2-3), then write this
   // wave's WTM x WTN results into the staging tile C (row pitch CPITCH, rows
@@ -410,34 +434,279 @@ hipError_t launch(const GemmParams& host, const GemmParams* dev, hipStream_t s) 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision engines: FP32 operands in HBM, 16-bit MFMA inside.
+//   split-BF16: x = x_hi + x_lo with x_hi = bf16(x), x_lo = bf16(x - x_hi)
+//               (round to nearest even); X Y ~ Xh Yh + Xh Yl + Xl Yh, three
+//               v_mfma_f32_32x32x16_bf16 per fragment pair, FP32 accumulate.
+//               BF16 has FP32's exponent range, so no operand scaling is used.
+//   scaled FP16: x -> fp16(x * 2^sx) with 2^sx putting max|X| in [2^14, 2^15);
+//               one v_mfma_f32_32x32x16_f16 per fragment pair; the product is
+//               multiplied by 2^-(sx+sy) (exact) before the epilogue.
+// The conversion happens between the global load and the LDS store, so HBM
+// and L2 only ever see FP32.  v_mfma_f32_32x32x16_{bf16,f16} lanes:
+//   A[i][k]: i = l&31, k = 8 (l>>5) + e;  B[k][j]: j = l&31, k = 8 (l>>5) + e
+//   D[8 (r>>2) + 4 (l>>5) + (r&3)][l&31], r = 0..15
+// Both operands are stored k-contiguous in LDS ([row][k] for X, [col][k] for
+// Y) so each lane's eight k values are one 16-byte read.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+template <int NWM_, int NWN_, int NI_, int NJ_, bool SPLIT_>
+struct PolLow {
+  static constexpr bool SPLIT = SPLIT_;
+  static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
+  static constexpr int WTM = 32 * NI, WTN = 32 * NJ;
+  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 32;
+  static constexpr int THREADS = 64 * NWM * NWN;
+  static constexpr int PLANES = SPLIT ? 2 : 1;
+  static constexpr int KP = BK + 8;                 // LDS row pitch, 16-bit elements
+  static constexpr int A_ELEMS = PLANES * BM * KP, B_ELEMS = PLANES * BN * KP;
+  using CT = float;
+};
+
+__device__ __forceinline__ float pow2f(int e) { return __int_as_float((e + 127) << 23); }
+
+// exponent e with 2^e <= x < 2^(e+1) for the max-abs float bits (0 -> 0)
+__device__ __forceinline__ int amax_exponent(const unsigned* amax) {
+  if (!amax) return 0;
+  const unsigned b = *amax;
+  return b ? (int)((b >> 23) & 0xff) - 127 : 0;
+}
+
+// split 8 floats into bf16 hi / lo (or scaled fp16 in `hi`)
+template <bool SPLIT>
+__device__ __forceinline__ void convert8(const float (&x)[8], float scale, u16x8& hi, u16x8& lo) {
+  if constexpr (SPLIT) {
+    bf16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 t = (__bf16)x[e];
+      h[e] = t;
+      l[e] = (__bf16)(x[e] - (float)t);
+    }
+    hi = __builtin_bit_cast(u16x8, h);
+    lo = __builtin_bit_cast(u16x8, l);
+  } else {
+    f16x8 h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) h[e] = (_Float16)(x[e] * scale);
+    hi = __builtin_bit_cast(u16x8, h);
+    lo = hi;
+  }
+}
+
+template <class Q>
+__global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs args) {
+  constexpr int STAGE_ELEMS = 2 * (Q::A_ELEMS + Q::B_ELEMS);                 // 16-bit
+  constexpr int CPITCH = Q::BN + 4;
+  constexpr int EPI_ELEMS = (Q::WTM * CPITCH * 4 + 1) / 2;
+  constexpr int SMEM = STAGE_ELEMS > EPI_ELEMS ? STAGE_ELEMS : EPI_ELEMS;
+  __shared__ __align__(16) unsigned short smem[SMEM];
+  // stage b: A planes at b * A_ELEMS, B planes at 2 * A_ELEMS + b * B_ELEMS
+
+  // loader items: A item = (row, k-group of 8), B item = (col, k-group of 8)
+  constexpr int KG = Q::BK / 8;
+  constexpr int NA = Q::BM * KG / Q::THREADS, NB = Q::BN * KG / Q::THREADS;
+  static_assert((Q::BM * KG) % Q::THREADS == 0 && (Q::BN * KG) % Q::THREADS == 0, "loader");
+
+  const int n = args.n, ld = args.ld;
+  const int tiles_m = n / Q::BM, tiles_n = n / Q::BN;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int row0 = tm * Q::BM, col0 = tn * Q::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / Q::NWN, wn = wave % Q::NWN;
+  const float* __restrict__ Xp = static_cast<const float*>(args.X);
+  const float* __restrict__ Yp = static_cast<const float*>(args.Y);
+
+  float sx = 1.f, sy = 1.f, unscale = 1.f;
+  if constexpr (!Q::SPLIT) {
+    const int ex = amax_exponent(args.epi->xamax), ey = amax_exponent(args.epi->yamax);
+    sx = pow2f(14 - ex);
+    sy = pow2f(14 - ey);
+    unscale = pow2f(ex - 14) * pow2f(ey - 14);
+  }
+
+  // A items: consecutive threads take consecutive k-groups of a row (row-contiguous
+  // 32-byte global reads); B items: consecutive threads take consecutive columns
+  // (each of the eight k rows is a 256-byte coalesced read per wave)
+  size_t ga[NA], gb[NB];
+  int la[NA], lb[NB];
+#pragma unroll
+  for (int it = 0; it < NA; ++it) {
+    const int v = tid + it * Q::THREADS, r = v / KG, g = v % KG;
+    ga[it] = (size_t)(row0 + r) * ld + 8 * g;
+    la[it] = r * Q::KP + 8 * g;
+  }
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int v = tid + it * Q::THREADS, c = v % Q::BN, g = v / Q::BN;
+    gb[it] = (size_t)(8 * g) * ld + col0 + c;
+    lb[it] = c * Q::KP + 8 * g;
+  }
+  float ra[NA][8], rb[NB][8];
+
+  auto gload = [&](int kc) {
+    const size_t ka = (size_t)kc * Q::BK, kb = ka * ld;
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
+      const float4 u = *reinterpret_cast<const float4*>(Xp + ga[it] + ka);
+      const float4 w = *reinterpret_cast<const float4*>(Xp + ga[it] + ka + 4);
+      ra[it][0] = u.x; ra[it][1] = u.y; ra[it][2] = u.z; ra[it][3] = u.w;
+      ra[it][4] = w.x; ra[it][5] = w.y; ra[it][6] = w.z; ra[it][7] = w.w;
+    }
+#pragma unroll
+    for (int it = 0; it < NB; ++it)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[it][e] = Yp[gb[it] + kb + (size_t)e * ld];
+  };
+  auto lstore = [&](int stage) {
+    unsigned short* As = smem + stage * Q::A_ELEMS;
+    unsigned short* Bs = smem + 2 * Q::A_ELEMS + stage * Q::B_ELEMS;
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
+      u16x8 h, l;
+      convert8<Q::SPLIT>(ra[it], sx, h, l);
+      *reinterpret_cast<u16x8*>(As + la[it]) = h;
+      if constexpr (Q::SPLIT) *reinterpret_cast<u16x8*>(As + Q::BM * Q::KP + la[it]) = l;
+    }
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      u16x8 h, l;
+      convert8<Q::SPLIT>(rb[it], sy, h, l);
+      *reinterpret_cast<u16x8*>(Bs + lb[it]) = h;
+      if constexpr (Q::SPLIT) *reinterpret_cast<u16x8*>(Bs + Q::BN * Q::KP + lb[it]) = l;
+    }
+  };
+
+  f32x16 acc[Q::NI][Q::NJ];
+#pragma unroll
+  for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+    for (int j = 0; j < Q::NJ; ++j) acc[i][j] = f32x16{};
+
+  const int nk = n / Q::BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int fr = lane & 31, fk = 8 * (lane >> 5);
+  for (int kc = 0; kc < nk; ++kc) {
+    const int cur = kc & 1;
+    gload(min(kc + 1, nk - 1));     // unconditional prefetch (see the FP64/FP32 kernel)
+    const unsigned short* As = smem + cur * Q::A_ELEMS;
+    const unsigned short* Bs = smem + 2 * Q::A_ELEMS + cur * Q::B_ELEMS;
+#pragma unroll
+    for (int ks = 0; ks < Q::BK / 16; ++ks) {
+      u16x8 ah[Q::NI], al[Q::NI], bh[Q::NJ], bl[Q::NJ];
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i) {
+        const int off = (wm * Q::WTM + 32 * i + fr) * Q::KP + 16 * ks + fk;
+        ah[i] = *reinterpret_cast<const u16x8*>(As + off);
+        if constexpr (Q::SPLIT) al[i] = *reinterpret_cast<const u16x8*>(As + Q::BM * Q::KP + off);
+      }
+#pragma unroll
+      for (int j = 0; j < Q::NJ; ++j) {
+        const int off = (wn * Q::WTN + 32 * j + fr) * Q::KP + 16 * ks + fk;
+        bh[j] = *reinterpret_cast<const u16x8*>(Bs + off);
+        if constexpr (Q::SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(Bs + Q::BN * Q::KP + off);
+      }
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+        for (int j = 0; j < Q::NJ; ++j) {
+          if constexpr (Q::SPLIT) {
+            const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]), Al = __builtin_bit_cast(bf16x8, al[i]);
+            const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]), Bl = __builtin_bit_cast(bf16x8, bl[j]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[i][j], 0, 0, 0);
+          } else {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, ah[i]),
+                                                              __builtin_bit_cast(f16x8, bh[j]),
+                                                              acc[i][j], 0, 0, 0);
+          }
+        }
+    }
+    lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: stage FP32 results per wave-row pass, apply the affine outputs
+  const GemmParams& p = *args.epi;
+  float* C = reinterpret_cast<float*>(smem);
+  constexpr int VEC = 4, VPR = Q::BN / VEC;
+  EpiState st{0.0, 0.f, 0};
+#pragma unroll 1
+  for (int pass = 0; pass < Q::NWM; ++pass) {
+    if (wm == pass) {
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+        for (int j = 0; j < Q::NJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            C[(32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * CPITCH + wn * Q::WTN + 32 * j + (lane & 31)] =
+                acc[i][j][r] * unscale;
+    }
+    __syncthreads();
+    for (int v = tid; v < Q::WTM * VPR; v += Q::THREADS) {
+      const int r = v / VPR, cv = (v % VPR) * VEC;
+      double c[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
+      epi_vec<VEC>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
+    }
+    __syncthreads();
+  }
+  publish_stats<Q::THREADS>(p, st, reinterpret_cast<double*>(smem));
+}
+
+template <class Q>
+hipError_t launch_low(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
+  if (host.n % Q::BM || host.n % Q::BN || host.n % Q::BK) return hipErrorInvalidValue;
+  const int grid = (host.n / Q::BM) * (host.n / Q::BN);
+  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
+  hipLaunchKernelGGL(gemm_lowp_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 // tile choices
-using F64Big = PolF64<2, 4, 8, 8>;     // 64 x 128 tile, 8 waves
-using F64Small = PolF64<2, 2, 4, 4>;   // 32 x 32 tile, 4 waves
-using F32Big = PolF32<2, 2, 4, 4>;     // 128 x 128 tile, 4 waves
+using F64Big = PolF64<2, 4, 8, 8, 1>;     // 64 x 128 tile, k-chunk 16, 8 waves
+using F64Small = PolF64<2, 2, 4, 4, 1>;   // 32 x 32 tile, k-chunk 16, 4 waves
+using F32Big = PolF32<2, 2, 4, 8>;     // 128 x 256 tile, 4 waves
 using F32Small = PolF32<2, 2, 2, 2>;   // 64 x 64 tile, 4 waves
 
 constexpr int kBigMin = 2048;          // n from which the large tiles are used
 
 }  // namespace
 
-hipError_t launch_gemm_lowp(Engine e, const GemmParams& host, const GemmParams* dev,
-                            hipStream_t s);  // gemm_lowp.hip
-int engine_tile_lowp(Engine e, int n);
+using BF3Big = PolLow<2, 4, 2, 2, true>;    // 128 x 256 tile, 8 waves
+using BF3Small = PolLow<2, 2, 1, 1, true>;  // 64 x 64 tile
+using H16Big = PolLow<2, 2, 2, 2, false>;   // 128 x 128 tile, 4 waves
+using H16Small = PolLow<2, 2, 1, 1, false>;
 
 int engine_tile(Engine e, int n) {
   switch (e) {
     case ENG_F64: return n >= kBigMin ? 128 : 32;
-    case ENG_F32: return n >= kBigMin ? 128 : 64;
-    default: return engine_tile_lowp(e, n);
+    case ENG_F32: return n >= kBigMin ? 256 : 64;
+    case ENG_BF16X3:
+    case ENG_F16S: return n >= kBigMin ? 256 : 64;
   }
+  return 256;
 }
 
 hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s) {
   switch (e) {
     case ENG_F64: return host.n >= kBigMin ? launch<F64Big>(host, dev, s) : launch<F64Small>(host, dev, s);
     case ENG_F32: return host.n >= kBigMin ? launch<F32Big>(host, dev, s) : launch<F32Small>(host, dev, s);
-    default: return launch_gemm_lowp(e, host, dev, s);
+    case ENG_BF16X3: return host.n >= kBigMin ? launch_low<BF3Big>(host, dev, s) : launch_low<BF3Small>(host, dev, s);
+    case ENG_F16S: return host.n >= kBigMin ? launch_low<H16Big>(host, dev, s) : launch_low<H16Small>(host, dev, s);
   }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace ns

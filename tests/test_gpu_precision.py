@@ -1,0 +1,83 @@
+"""GPU parity of the mixed-precision forms against the FP64 oracle.
+
+Mixed forms read A in FP64, run the bulk products as FP32, split-BF16 (three
+BF16 products) or scaled FP16 on the matrix cores with FP32 accumulation, and
+keep FP64 for the running sum (S or Y) and, in the residual methods, for the
+residual product R = I - (I - A) Y.  Bars (relative Frobenius error against
+the FP64 oracle of the same method): FP32 1e-5, split-BF16 1e-4; scaled FP16
+has no stated bar and is held to 1e-2 here (its measured error is printed).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import series
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32_acc64": 1e-5, "split_bf16": 1e-4, "f16_scaled": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def ns():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_11843_amd as ns
+    return ns
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(ns, A, k, method, dtype):
+    say(f"[gpu] {method} {dtype} n={A.shape[0]} k={k}")
+    out, rep = ns.ns_eval_ex(torch.from_numpy(np.ascontiguousarray(A)).cuda(), k, method, dtype,
+                             report=True)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("dtype", ["f32_acc64", "split_bf16", "f16_scaled"])
+@pytest.mark.parametrize("method", ["binary", "radix9", "quinary", "radix15", "radix9_resid", "hensel"])
+@pytest.mark.parametrize("n", [64, 300])
+def test_mixed_precision_parity(ns, method, dtype, n):
+    w = workloads.symmetric(n, 0.9, 200 + n)
+    k = 729
+    got, rep = run(ns, w.A, k, method, dtype)
+    ref, orep = series.evaluate(w.A, k, method)
+    err = series.rel_fro(got, ref)
+    say(f"   rel err {err:.3e}")
+    assert err < TOL[dtype]
+    assert rep["gemms_performed"] == orep["products"]
+    assert not rep["nonfinite"]
+
+
+@pytest.mark.parametrize("dtype", ["f32_acc64", "split_bf16", "f16_scaled"])
+@pytest.mark.parametrize("method", ["radix9", "radix9_resid", "radix15"])
+def test_mixed_precision_large_tiles(ns, method, dtype):
+    """n = 2048 runs the large-tile engines (the n = 8192 workload's kernels)."""
+    w = workloads.symmetric(2048, 0.9, 4)
+    k = 729 if method != "radix15" else 3375
+    got, rep = run(ns, w.A, k, method, dtype)
+    ref = series.spectral_form(w.Q, w.lam, rep["k_eff"], cols=np.arange(0, 2048, 97))
+    err = series.rel_fro(got[:, 0:2048:97], ref)
+    say(f"   sampled rel err {err:.3e}")
+    assert err < TOL[dtype]
+
+
+def test_residual_form_corrects_low_precision(ns):
+    """The residual iteration with an FP64 residual recovers accuracy the
+    telescoping form cannot: its error is far below the FP16 products'."""
+    w = workloads.symmetric(300, 0.9, 9)
+    tele, _ = run(ns, w.A, 729, "radix9", "f16_scaled")
+    resid, _ = run(ns, w.A, 729, "radix9_resid", "f16_scaled")
+    ref, _ = series.radix9(w.A, 729)
+    e_t, e_r = series.rel_fro(tele, ref), series.rel_fro(resid, ref)
+    say(f"   telescoping {e_t:.3e}  residual {e_r:.3e}")
+    assert e_r < e_t / 10
