@@ -660,6 +660,12 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   return NS_OK;
 }
 
+// accessors for batched.hip
+int batch_fail(int status, const char* msg) { return fail(status, "%s", msg); }
+void* handle_batched_state(ns_handle* h) { return h->batched; }
+void set_handle_batched_state(ns_handle* h, void* st) { h->batched = st; }
+int handle_device(ns_handle* h) { return h->device; }
+
 }  // namespace ns
 
 // ---------------------------------------------------------------------------

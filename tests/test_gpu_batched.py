@@ -1,0 +1,163 @@
+"""GPU parity of the batched form (one persistent launch, cached HIP graph)
+against the oracle and against the per-matrix launch loop."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import series
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ns():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_11843_amd as ns
+    return ns
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pack(mats):
+    offs = np.zeros(len(mats), dtype=np.int64)
+    total = 0
+    for i, M in enumerate(mats):
+        offs[i] = total
+        total += M.size
+    buf = np.zeros(total, dtype=np.float32)
+    for i, M in enumerate(mats):
+        buf[offs[i]:offs[i] + M.size] = M.astype(np.float32).ravel()
+    return buf, offs
+
+
+def unpack(buf, offs, ns_):
+    return [buf[o:o + n * n].reshape(n, n) for o, n in zip(offs, ns_)]
+
+
+def device_batch(mats):
+    buf, offs = pack(mats)
+    ns_ = np.array([M.shape[0] for M in mats], dtype=np.int32)
+    return (torch.from_numpy(buf).cuda(), torch.from_numpy(offs).cuda(),
+            torch.from_numpy(ns_).cuda(), torch.from_numpy(ns_), offs, ns_)
+
+
+def mixed_batch(seed=0):
+    rng = np.random.default_rng(seed)
+    sizes = [1, 8, 13, 16, 32, 50, 64, 65, 100, 128, 129, 200, 256] * 3
+    rng.shuffle(sizes)
+    return [workloads.jacobi(int(n), rng) for n in sizes]
+
+
+@pytest.mark.parametrize("method", ["radix9", "binary", "naive"])
+def test_batched_matches_oracle(ns, method):
+    mats = mixed_batch(1)
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    k = 20 if method == "naive" else 81
+    say(f"[gpu] batched {method} batch={len(mats)} k={k}")
+    out, rep = ns.ns_eval_batched(A, offd, nd, nh, k, method, "f32", report=True)
+    torch.cuda.synchronize()
+    got = unpack(out.cpu().numpy(), offs, ns_)
+    worst = 0.0
+    for M, G in zip(mats, got):
+        ref, _ = series.evaluate(M.astype(np.float32).astype(np.float64), k, method)
+        worst = max(worst, series.rel_fro(G, ref))
+    say(f"   worst rel err {worst:.3e}")
+    assert worst < 1e-5
+    assert not rep["nonfinite"]
+    assert rep["gemms_performed"] == ns.ns_plan(k, method)[2]
+
+
+def test_batched_bit_identical_to_launch_loop(ns):
+    """Same tile arithmetic, same padding: the persistent kernel and the
+    per-matrix launch loop must agree bit for bit."""
+    mats = mixed_batch(2)
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    say(f"[gpu] batched vs loop batch={len(mats)}")
+    a = ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32")
+    b = ns.ns_eval_batched_loop(A, torch.from_numpy(offs), nh, 81, "radix9", "f32")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_graph_replays_are_identical(ns):
+    """The cached graph is replayed with unrelated device work and host
+    synchronisation in between; every replay must equal the first result."""
+    mats = mixed_batch(3)
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    h = ns.Handle(0)
+    out = torch.empty_like(A)
+    first = ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", out_packed=out, handle=h).clone()
+    for i in range(4):
+        x = torch.randn(512, 512, device="cuda")
+        (x @ x).sum().item()                      # other work between replays
+        out.zero_()
+        ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", out_packed=out, handle=h)
+        torch.cuda.synchronize()
+        assert torch.equal(out, first), f"replay {i}"
+    h.close()
+
+
+def test_batched_k1_identity_and_empty(ns):
+    mats = mixed_batch(4)[:10]
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    out = ns.ns_eval_batched(A, offd, nd, nh, 1, "radix9", "f32")
+    torch.cuda.synchronize()
+    for G, n in zip(unpack(out.cpu().numpy(), offs, ns_), ns_):
+        assert np.array_equal(G, np.eye(n))
+    empty = torch.zeros(1, device="cuda")
+    z = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ns.ns_eval_batched(empty, z, z.int(), torch.zeros(0, dtype=torch.int32), 81, "radix9", "f32",
+                       out_packed=empty)
+
+
+def test_batched_rejects_unsupported(ns):
+    mats = [np.eye(300) * 0.5]
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    with pytest.raises(ns.NSError) as e:
+        ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32")
+    assert e.value.status == -2
+    with pytest.raises(ns.NSError) as e:
+        ns.ns_eval_batched(A, offd, nd, nh, 81, "radix15", "f32")
+    assert e.value.status == -2
+
+
+def test_autotune_then_evaluate(ns, tmp_path, monkeypatch):
+    monkeypatch.setenv("NS_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    mats = mixed_batch(5)
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    h = ns.Handle(0)
+    out = torch.empty_like(A)
+    say("[gpu] autotune")
+    n_timed = ns.ns_autotune_batched(A, offd, nd, nh, 81, out, handle=h)
+    assert n_timed >= 1
+    got = ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", out_packed=out, handle=h)
+    ref = ns.ns_eval_batched_loop(A, torch.from_numpy(offs), nh, 81, "radix9", "f32", handle=h)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert (tmp_path / "tune.jsonl").read_text().count("\"big\"") == 1
+    h.close()
+
+
+@pytest.mark.slow
+def test_jacobi_batch_workload(ns):
+    """The 2048-matrix workload in full against the oracle, matrix by matrix."""
+    w = workloads.make("jacobi_batch")
+    A, offd, nd, nh, offs, ns_ = device_batch(w.mats)
+    say(f"[gpu] jacobi_batch batch={len(w.mats)}")
+    out, rep = ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", report=True)
+    torch.cuda.synchronize()
+    got = unpack(out.cpu().numpy(), offs, ns_)
+    worst = 0.0
+    for M, G in zip(w.mats, got):
+        ref, _ = series.radix9(M.astype(np.float32).astype(np.float64), 81)
+        worst = max(worst, series.rel_fro(G, ref))
+    say(f"   worst rel err {worst:.3e}")
+    assert worst < 1e-5
