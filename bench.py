@@ -128,6 +128,31 @@ def cpu_oracle_sample(fn, label, flops):
                  "kind": "oracle", "sample": f"{label} ({sec:.2f} s, {cpu_model()})"}
 
 
+def measured_traffic(summary="pmc_product_f64_large_symmetric.md"):
+    """HBM-side bytes per launch of the FP64 product kernel from the committed
+    rocprofv3 counter summary, or None once the kernel source has changed
+    since the counters were taken (the summary records a source hash)."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", summary)
+    try:
+        vals = {}
+        with open(path) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 2 and parts[0] in ("source_sha256_16", "traffic_bytes_per_launch"):
+                    vals[parts[0]] = parts[1]
+        h = hashlib.sha256()
+        for f in ("gemm_device.h", "gemm.hip"):
+            with open(os.path.join(root, "paper_2602_11843_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if vals.get("source_sha256_16") != h.hexdigest()[:16]:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline_from_leg(leg, n, kernel, dtype, mfma_per_logical=1.0):
     if not leg.get("product_launches"):
         return None
@@ -199,6 +224,9 @@ def bench_large_symmetric(args, torch, ns):
     line["predicted_speedup_by_product_count"] = round(20 / 15, 4)
     kern = "gemm_kernel<PolF64<2,4,8,8,1>>" if key[1] == "f64" else "gemm_kernel<PolF32<2,2,4,8>>"
     line["roofline"] = roofline_from_leg(main, n, kern, key[1])
+    if line["roofline"] and key == ("radix9", "f64"):
+        line["roofline"]["traffic"] = measured_traffic()
+        line["roofline"]["traffic_unit"] = "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)"
     line["cpu_baseline"] = cpu
     return line
 
