@@ -38,7 +38,7 @@ hipError_t launch_low(const GemmParams& host, const GemmParams* dev, hipStream_t
 }
 
 // tile choices
-using F64Big = PolF64<2, 4, 8, 8, 1>;     // 64 x 128 tile, k-chunk 16, 8 waves
+using F64Big = PolF64<2, 4, 8, 8, 2>;     // 64 x 128 tile, k-chunk 32, 8 waves
 using F64Small = PolF64<2, 2, 4, 4, 1>;   // 32 x 32 tile, k-chunk 16, 4 waves
 using F32Big = PolF32<2, 2, 4, 8>;     // 128 x 256 tile, 4 waves
 using F32Small = PolF32<2, 2, 2, 2>;   // 64 x 64 tile, 4 waves

@@ -179,6 +179,10 @@ struct PolF64 {
   // B reads touch 16 rows KS apart; a pitch of BN + 2 doubles puts rows
   // 2 apart 32 bytes apart in the banks (at most 2-way conflicts).
   static constexpr int BPITCH = BN + 2;
+  // stage the whole tile at once: with one pass per wave-row, a later
+  // wave-row would hold its accumulators through the earlier pass's epilogue
+  static constexpr int EPI_PASSES = 1;
+  static constexpr int DMA_STAGES = 2;    // LDS buffers of the direct-to-LDS k-loop
   struct Acc {
     double v[NI][NJ];
   };
@@ -207,17 +211,17 @@ struct PolF64 {
         for (int s = 0; s < KS; ++s) af[i][s] = src[s];
       }
     }
+    // B fragments are consumed one column block at a time, so only the A
+    // fragments and one B value are live next to the accumulators
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      double bf[NJ];
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) bf[j] = Bs[(KS * kk + s) * BPITCH + wn * WTN + 4 * j + q];
+      for (int j = 0; j < NJ; ++j) {
+        const double bf = Bs[(KS * kk + s) * BPITCH + wn * WTN + 4 * j + q];
 #pragma unroll
-      for (int i = 0; i < NI; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf[j], acc.v[i][j], 0, 0, 0);
-    }
+        for (int i = 0; i < NI; ++i)
+          acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf, acc.v[i][j], 0, 0, 0);
+      }
   }
   // Sum the four k-slices (lanes differing in bits 2-3), then write this
   // wave's WTM x WTN results into the staging tile C (row pitch CPITCH, rows
@@ -260,6 +264,8 @@ struct PolF32 {
   static constexpr int THREADS = 64 * NWM * NWN;
   static constexpr int APITCH = BK;       // a wave's A reads are one contiguous 1 KB run
   static constexpr int BPITCH = BN + 4;   // the 4 k-rows of a B read land in distinct banks
+  static constexpr int EPI_PASSES = NWM;  // stage one wave-row at a time (bounds the LDS)
+  static constexpr int DMA_STAGES = 2;    // LDS buffers of the direct-to-LDS k-loop
   struct Acc {
     f4 v[NI][NJ];
   };
@@ -315,6 +321,16 @@ struct MainArgs {
   const GemmParams* epi;
 };
 
+template <class P>
+struct DmaShape {
+  using T = typename P::T;
+  static constexpr int NW = P::THREADS / 64;
+  static constexpr int A_BYTES = P::BM * P::BK * (int)sizeof(T);
+  static constexpr int A_INS = A_BYTES / 1024;                 // wave instructions per X tile
+  static constexpr bool OK = P::BN * (int)sizeof(T) == 1024 && P::APITCH == P::BK &&
+                             A_BYTES % 1024 == 0 && A_INS % NW == 0 && P::BK % NW == 0;
+};
+
 // LDS elements (of P::T) a tile needs: two k-chunk stages, or one wave-row
 // of FP32/FP64 results for the epilogue, whichever is larger.
 template <class P>
@@ -323,8 +339,10 @@ constexpr int tile_smem_elems() {
   using CT = typename P::CT;
   constexpr int A_SZ = P::BM * P::APITCH, B_SZ = P::BK * P::BPITCH;
   constexpr int CPITCH = P::BN + 16 / (int)sizeof(CT);
-  constexpr int STAGE = (P::WTM * CPITCH * (int)sizeof(CT) + (int)sizeof(T) - 1) / (int)sizeof(T);
-  return 2 * (A_SZ + B_SZ) > STAGE ? 2 * (A_SZ + B_SZ) : STAGE;
+  constexpr int STAGE = (P::BM / P::EPI_PASSES * CPITCH * (int)sizeof(CT) + (int)sizeof(T) - 1) /
+                        (int)sizeof(T);
+  constexpr int LOOP = (DmaShape<P>::OK ? P::DMA_STAGES : 2) * (A_SZ + B_SZ);
+  return LOOP > STAGE ? LOOP : STAGE;
 }
 
 // acc += X[row0:row0+BM, :K] Y[:K, col0:col0+BN] with double-buffered LDS
@@ -391,11 +409,107 @@ __device__ __forceinline__ void tile_mainloop(const typename P::T* __restrict__ 
   }
 }
 
-// Epilogue of one tile in NWM passes: the waves of wave-row `pass` stage their
-// WTM x BN results in LDS, then the whole workgroup applies the affine outputs
-// to those rows with row-contiguous 16-byte vectors (coalesced Z reads and
-// output writes).  smem must be free on entry (tile_mainloop leaves it so)
-// and is free again on exit.
+// Direct-to-LDS variant of the k-loop for tiles whose Y-tile rows are exactly
+// 1 KB and whose X tile is unpadded: every 16-byte vector goes from global
+// memory straight into LDS (global_load_lds_dwordx4 writes lane l's 16 bytes
+// at a wave-uniform LDS address + 16 l), so a wave instruction fills one
+// contiguous 1 KB run.  The next chunk streams into the idle buffer while the
+// matrix cores work on the current one, with no staging registers.
+template <class P>
+struct DmaPlan {
+  using T = typename P::T;
+  using D = DmaShape<P>;
+  static constexpr int NA = D::A_INS / D::NW, NB = P::BK / D::NW;
+  uint32_t a_off[NA];         // element offsets of this lane's vectors, chunk 0
+  uint32_t b_off[NB];
+  int a_lds[NA], b_lds[NB];   // wave-uniform LDS element offsets within a buffer
+  __device__ __forceinline__ void init(int ld, int row0, int col0) {
+    constexpr int EPV = 16 / (int)sizeof(T);
+    constexpr int ROW_VEC = P::BK / EPV;               // 16-byte vectors per X-tile row
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int ins = wave + i * D::NW;                // this instruction's 1 KB run of the X tile
+      const int v = ins * 64 + lane, r = v / ROW_VEC, c = (v % ROW_VEC) * EPV;
+      a_off[i] = (uint32_t)((row0 + r) * ld + c);
+      a_lds[i] = ins * (1024 / (int)sizeof(T));
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int r = wave + i * D::NW;                  // one Y-tile row per instruction
+      b_off[i] = (uint32_t)(r * ld + col0 + lane * EPV);
+      b_lds[i] = r * P::BPITCH;
+    }
+  }
+  // issue the loads of k-chunk kc into the LDS buffers As / Bs
+  __device__ __forceinline__ void issue(const T* __restrict__ Xp, const T* __restrict__ Yp, int ld,
+                                        int kc, T* As, T* Bs) const {
+    const T* xa = Xp + (size_t)kc * P::BK;
+    const T* yb = Yp + (size_t)kc * P::BK * ld;
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(xa + a_off[i]),
+                                       (__attribute__((address_space(3))) void*)(As + a_lds[i]), 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(yb + b_off[i]),
+                                       (__attribute__((address_space(3))) void*)(Bs + b_lds[i]), 16, 0, 0);
+  }
+};
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt in bits 3:0, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
+template <class P>
+__device__ __forceinline__ void tile_mainloop_dma(const typename P::T* __restrict__ Xp,
+                                                  const typename P::T* __restrict__ Yp, int ld, int K,
+                                                  int row0, int col0, typename P::T* smem,
+                                                  typename P::Acc& acc) {
+  constexpr int A_SZ = P::BM * P::APITCH, B_SZ = P::BK * P::BPITCH;
+  constexpr int S = P::DMA_STAGES;
+  constexpr int PER_CHUNK = DmaPlan<P>::NA + DmaPlan<P>::NB;   // this wave's loads per chunk
+  static_assert(S == 2 || S == 3, "two or three LDS stages");
+  // buffer b: X tile at smem + b * A_SZ, Y tile at smem + S * A_SZ + b * B_SZ
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / P::NWN, wn = wave % P::NWN;
+  const int nk = K / P::BK;
+  DmaPlan<P> plan;
+  plan.init(ld, row0, col0);
+  for (int c = 0; c < S - 1 && c < nk; ++c)
+    plan.issue(Xp, Yp, ld, c, smem + c * A_SZ, smem + S * A_SZ + c * B_SZ);
+  if constexpr (S == 3) {
+    if (nk > 1) wait_vmcnt<PER_CHUNK>();   // chunk 0 landed, chunk 1 may still fly
+    else wait_vmcnt<0>();
+  } else {
+    wait_vmcnt<0>();
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int kc = 0; kc < nk; ++kc) {
+    // the buffer of chunk kc + S - 1 was last read in iteration kc - 1, which
+    // every wave has finished (barrier at its end)
+    const int nxt = kc + S - 1;
+    const int nb = cur + S - 1 >= S ? cur - 1 : cur + S - 1;
+    if (nxt < nk) plan.issue(Xp, Yp, ld, nxt, smem + nb * A_SZ, smem + S * A_SZ + nb * B_SZ);
+    P::chunk(smem + cur * A_SZ, smem + S * A_SZ + cur * B_SZ, acc, wm, wn, lane);
+    // chunk kc + 1 must be in LDS before the barrier; newer loads may stay in flight
+    if (S == 3 && nxt < nk) wait_vmcnt<PER_CHUNK>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    cur = cur + 1 == S ? 0 : cur + 1;
+  }
+}
+
+// Epilogue of one tile in EPI_PASSES passes: the waves whose rows fall in the
+// pass stage their results in LDS, then the whole workgroup applies the
+// affine outputs to those rows with row-contiguous 16-byte vectors (coalesced
+// Z reads and output writes).  smem must be free on entry (the k-loops leave
+// it so) and is free again on exit.
 template <class P>
 __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmParams& p, int row0,
                                               int col0, typename P::T* smem, EpiState& st) {
@@ -403,19 +517,21 @@ __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmPa
   constexpr int CPITCH = P::BN + 16 / (int)sizeof(CT);
   constexpr int VEC = 16 / (int)sizeof(CT);          // 2 doubles or 4 floats
   constexpr int VPR = P::BN / VEC;                   // vectors per row
+  constexpr int WROWS = P::NWM / P::EPI_PASSES;      // wave-rows per pass
+  constexpr int PROWS = WROWS * P::WTM;              // tile rows per pass
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / P::NWN, wn = wave % P::NWN;
   CT* C = reinterpret_cast<CT*>(smem);
 #pragma unroll 1
-  for (int pass = 0; pass < P::NWM; ++pass) {
-    if (wm == pass) P::stage(acc, lane, wn, C, CPITCH);
+  for (int pass = 0; pass < P::EPI_PASSES; ++pass) {
+    if (wm / WROWS == pass) P::stage(acc, lane, wn, C + (wm % WROWS) * P::WTM * CPITCH, CPITCH);
     __syncthreads();
-    for (int v = tid; v < P::WTM * VPR; v += P::THREADS) {
+    for (int v = tid; v < PROWS * VPR; v += P::THREADS) {
       const int r = v / VPR, cv = (v % VPR) * VEC;
       double c[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
-      epi_vec<VEC>(p, row0 + pass * P::WTM + r, col0 + cv, c, st);
+      epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
     }
     __syncthreads();
   }
@@ -431,8 +547,12 @@ __global__ __launch_bounds__(P::THREADS) void gemm_kernel(const MainArgs args) {
   const int row0 = tm * P::BM, col0 = tn * P::BN;
   typename P::Acc acc;
   P::zero(acc);
-  tile_mainloop<P>(static_cast<const T*>(args.X), static_cast<const T*>(args.Y), args.ld, args.n,
-                   row0, col0, smem, acc);
+  if constexpr (DmaShape<P>::OK)
+    tile_mainloop_dma<P>(static_cast<const T*>(args.X), static_cast<const T*>(args.Y), args.ld,
+                         args.n, row0, col0, smem, acc);
+  else
+    tile_mainloop<P>(static_cast<const T*>(args.X), static_cast<const T*>(args.Y), args.ld, args.n,
+                     row0, col0, smem, acc);
   // the epilogue parameters are read from device memory only now, so they
   // occupy no registers while the matrix cores run
   const GemmParams& p = *args.epi;
