@@ -78,7 +78,7 @@ __device__ __forceinline__ void wg_product(const float* X, const float* Y, int n
     typename P::Acc acc;
     P::zero(acc);
     tile_mainloop<P>(X, Y, np, np, row0, col0, smem, acc);
-    tile_epilogue<P>(acc, ep, row0, col0, smem, st);
+    tile_epilogue<P, true>(acc, ep, row0, col0, smem, st);   // all slot matrices are FP32
   }
   publish_stats<kThreads>(ep, st, reinterpret_cast<double*>(smem));
   __syncthreads();

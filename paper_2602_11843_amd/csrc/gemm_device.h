@@ -3,6 +3,8 @@
 // policies, the LDS-staged fused epilogue and the low-precision kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace ns {
@@ -119,6 +121,65 @@ __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, c
       }
     }
   }
+}
+
+// The same epilogue when every Z input and every output is FP32: float
+// arithmetic, no per-element type branches (fewer registers; used by the FP32
+// engine whenever a product's inputs and outputs are all FP32, and always by
+// the batched kernel, so both produce identical bits).
+template <int VEC>
+__device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int col,
+                                            const double (&c)[VEC], EpiState& st) {
+  static_assert(VEC == 4, "float epilogue works on float4 vectors");
+  const size_t idx = (size_t)row * p.ld + col;
+  float z[kMaxZ][VEC];
+#pragma unroll
+  for (int i = 0; i < kMaxZ; ++i) {
+    if (i < p.nz) {
+      const float4 t = *reinterpret_cast<const float4*>(static_cast<const float*>(p.Z[i]) + idx);
+      z[i][0] = t.x; z[i][1] = t.y; z[i][2] = t.z; z[i][3] = t.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) z[i][e] = 0.f;
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < kMaxOut; ++o) {
+    if (o >= p.no) break;
+    const EpiOut& e = p.out[o];
+    const float a = (float)e.a, id = (float)e.id;
+    float zc[kMaxZ];
+#pragma unroll
+    for (int i = 0; i < kMaxZ; ++i) zc[i] = (float)e.z[i];
+    float y[VEC];
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) {
+      y[t] = a * (float)c[t] + ((row == col + t) ? id : 0.f);
+#pragma unroll
+      for (int i = 0; i < kMaxZ; ++i) y[t] += zc[i] * z[i][t];
+    }
+    *reinterpret_cast<float4*>(static_cast<float*>(e.ptr) + idx) = make_float4(y[0], y[1], y[2], y[3]);
+    if (o == 0) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) {
+        st.ssq += (double)y[t] * (double)y[t];
+        if (!isfinite(y[t])) st.bad = 1;
+        st.amax = fmaxf(st.amax, fabsf(y[t]));
+      }
+    }
+  }
+}
+
+// true if every Z input and output of the block is FP32
+__device__ __forceinline__ bool all_f32(const GemmParams& p) {
+  bool f = true;
+#pragma unroll
+  for (int i = 0; i < kMaxZ; ++i)
+    if (i < p.nz && p.zf64[i]) f = false;
+#pragma unroll
+  for (int o = 0; o < kMaxOut; ++o)
+    if (o < p.no && p.out[o].f64) f = false;
+  return f;
 }
 
 // Reduce the per-thread statistics over the workgroup and publish them with
@@ -510,7 +571,7 @@ __device__ __forceinline__ void tile_mainloop_dma(const typename P::T* __restric
 // affine outputs to those rows with row-contiguous 16-byte vectors (coalesced
 // Z reads and output writes).  smem must be free on entry (the k-loops leave
 // it so) and is free again on exit.
-template <class P>
+template <class P, bool F32 = false>
 __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmParams& p, int row0,
                                               int col0, typename P::T* smem, EpiState& st) {
   using CT = typename P::CT;
@@ -531,7 +592,8 @@ __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmPa
       double c[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
-      epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+      if constexpr (F32) epi_vec_f32<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+      else epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
     }
     __syncthreads();
   }
@@ -557,7 +619,12 @@ __global__ __launch_bounds__(P::THREADS) void gemm_kernel(const MainArgs args) {
   // occupy no registers while the matrix cores run
   const GemmParams& p = *args.epi;
   EpiState st{0.0, 0.f, 0};
-  tile_epilogue<P>(acc, p, row0, col0, smem, st);
+  if constexpr (std::is_same<typename P::CT, float>::value) {
+    if (all_f32(p)) tile_epilogue<P, true>(acc, p, row0, col0, smem, st);
+    else tile_epilogue<P, false>(acc, p, row0, col0, smem, st);
+  } else {
+    tile_epilogue<P, false>(acc, p, row0, col0, smem, st);
+  }
   publish_stats<P::THREADS>(p, st, reinterpret_cast<double*>(smem));
 }
 
