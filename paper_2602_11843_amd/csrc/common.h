@@ -57,6 +57,20 @@ int engine_tile(Engine e, int n);
 // reads the epilogue part from there).  Returns hipSuccess or the launch error.
 hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t stream);
 
+// Low-precision products at large n (panel.hip): each operand is first
+// rewritten into 16-bit panels (bf16 hi/lo planes, or one scaled fp16 plane),
+// X by rows and Y by columns, then multiplied from the panels.
+constexpr int kPanelMin = 2048;
+bool panel_path(Engine e, int n);
+size_t panel_bytes(Engine e, int n);      // bytes of one operand's panels
+// dst <- panels of src (n x n, ld; row-major FP32).  transpose = 0 lays out the
+// rows of src (an X operand), 1 its columns (a Y operand).  amax: the max-abs
+// slot of src for the FP16 scale (scaled FP16 only).
+hipError_t launch_to_panels(Engine e, const float* src, int n, int ld, int transpose, void* dst,
+                            const unsigned* amax, hipStream_t s);
+// host.X / host.Y point at the panels of X (rows) and Y (columns).
+hipError_t launch_gemm_panels(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s);
+
 // Elementwise helpers (util.hip).
 // dst (padded n_pad x n_pad, ld n_pad) <- src (n x n, lda) converted; the
 // padding is zero.  *_f64 flags give element types.

@@ -47,9 +47,8 @@ constexpr int kBigMin = 2048;          // n from which the large tiles are used
 
 }  // namespace
 
-using BF3Big = PolLow<2, 4, 2, 2, true>;    // 128 x 256 tile, 8 waves
+// below kPanelMin the low-precision engines convert on the way into LDS
 using BF3Small = PolLow<2, 2, 1, 1, true>;  // 64 x 64 tile
-using H16Big = PolLow<2, 2, 2, 2, false>;   // 128 x 128 tile, 4 waves
 using H16Small = PolLow<2, 2, 1, 1, false>;
 
 int engine_tile(Engine e, int n) {
@@ -66,8 +65,9 @@ hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, 
   switch (e) {
     case ENG_F64: return host.n >= kBigMin ? launch<F64Big>(host, dev, s) : launch<F64Small>(host, dev, s);
     case ENG_F32: return host.n >= kBigMin ? launch<F32Big>(host, dev, s) : launch<F32Small>(host, dev, s);
-    case ENG_BF16X3: return host.n >= kBigMin ? launch_low<BF3Big>(host, dev, s) : launch_low<BF3Small>(host, dev, s);
-    case ENG_F16S: return host.n >= kBigMin ? launch_low<H16Big>(host, dev, s) : launch_low<H16Small>(host, dev, s);
+    // at n >= kPanelMin these engines run from panels (launch_gemm_panels)
+    case ENG_BF16X3: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<BF3Small>(host, dev, s);
+    case ENG_F16S: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<H16Small>(host, dev, s);
   }
   return hipErrorInvalidValue;
 }

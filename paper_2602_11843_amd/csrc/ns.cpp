@@ -194,6 +194,8 @@ void buffer_counts(int method, int dtype, int* nw, int* n64) {
     default: *nw = 0;
   }
   *n64 = mixed ? (is_residual(method) ? 2 : 1) : 0;    // Y64 + A64, or S64
+  // the 16-bit panels of a product's two operands (each at most an FP32 matrix)
+  if (dtype == NS_SPLIT_BF16 || dtype == NS_F16_SCALED) *nw += 2;
 }
 
 size_t workspace_bytes(int64_t n, int method, int dtype) {
@@ -223,12 +225,15 @@ struct Out {
 
 // A recorded device operation of a schedule.
 struct Op {
-  enum Kind { GEMM, IDENTITY, AMAX } kind;
+  enum Kind { GEMM, IDENTITY, AMAX, PANELS } kind;
   Engine e;
   GemmParams p;      // GEMM
-  void* ptr;         // IDENTITY / AMAX target
+  bool panels;       // GEMM: X / Y are 16-bit panels
+  void* ptr;         // IDENTITY / AMAX target, PANELS source
   int f64;
   unsigned* amax;
+  void* dst;         // PANELS destination
+  int transpose;     // PANELS: 1 for a Y operand
 };
 
 struct Ctx {
@@ -245,6 +250,7 @@ struct Ctx {
   char* arena;
   size_t arena_off = 0;
   std::vector<Op> ops;
+  Buf panel_x, panel_y;   // panels of the current product's operands (low precision, large n)
 
   Buf take(int f64) {
     Buf b;
@@ -281,6 +287,18 @@ struct Ctx {
     ops.push_back(op);
   }
 
+  void panels(Engine e, const Buf& src, int transpose, Buf& dst) {
+    if (!dst.p) dst = take(0);
+    Op op{};
+    op.kind = Op::PANELS;
+    op.e = e;
+    op.ptr = src.p;
+    op.amax = src.amax;
+    op.dst = dst.p;
+    op.transpose = transpose;
+    ops.push_back(op);
+  }
+
   // Record C = X Y on engine e; Z inputs; outputs as affine combinations of
   // (C, Z..., I).  norm_level >= 0 accumulates ||output 0||_F^2 there.
   void gemm(Engine e, const Buf& X, const Buf& Y, std::initializer_list<Buf> Z,
@@ -292,6 +310,13 @@ struct Ctx {
     GemmParams& p = op.p;
     p.X = X.p;
     p.Y = Y.p;
+    if (panel_path(e, np)) {
+      panels(e, X, 0, panel_x);
+      panels(e, Y, 1, panel_y);
+      p.X = panel_x.p;
+      p.Y = panel_y.p;
+      op.panels = true;
+    }
     p.n = np;
     p.ld = np;
     p.nz = 0;
@@ -370,6 +395,11 @@ struct Ctx {
         NS_HIP(launch_amax(static_cast<const float*>(op.ptr), (size_t)np * np, op.amax, s));
         continue;
       }
+      if (op.kind == Op::PANELS) {
+        NS_HIP(launch_to_panels(op.e, static_cast<const float*>(op.ptr), np, np, op.transpose, op.dst,
+                                op.amax, s));
+        continue;
+      }
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (h->timing) {
         if (h->ev_used + 2 > h->ev.size()) {
@@ -384,7 +414,8 @@ struct Ctx {
         h->ev_used += 2;
         NS_HIP(hipEventRecord(e0, s));
       }
-      const hipError_t err = launch_gemm(op.e, op.p, h->params_dev + gi, s);
+      const hipError_t err = op.panels ? launch_gemm_panels(op.e, op.p, h->params_dev + gi, s)
+                                       : launch_gemm(op.e, op.p, h->params_dev + gi, s);
       ++gi;
       if (err != hipSuccess) return fail(NS_ERR_HIP, "product launch failed: %s", hipGetErrorString(err));
       if (h->timing) {

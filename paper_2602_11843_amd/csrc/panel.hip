@@ -1,0 +1,326 @@
+// Low-precision products at large n from pre-split 16-bit panels.
+//
+// The split-BF16 and scaled-FP16 forms (FP32 operands in HBM, 16-bit MFMA
+// inside) first rewrite each operand once into 16-bit planes, then run a
+// product kernel whose k-loop is nothing but direct-to-LDS loads, 16-byte LDS
+// reads and MFMAs.  Converting in the k-loop instead would redo the split of
+// every X row panel once per output-tile column (n / BN times); here it is
+// done once per operand, by a pass bound by HBM bandwidth.
+//
+// Planes
+//   split-BF16:  x_hi = bf16_rne(x), x_lo = bf16_rne(x - x_hi); X Y is taken
+//                as Xh Yh + Xh Yl + Xl Yh with FP32 accumulation.
+//   scaled FP16: x_h = fp16_rne(x 2^sx), 2^sx placing max|X| in [2^14, 2^15);
+//                the product is multiplied by 2^-(sx+sy) (exact) before the
+//                epilogue.
+//
+// Panel layout of an operand M (n x n, n a multiple of 64): the product needs
+// M[r][k] for output row r (X: M = X; Y: M = Y^T, r the output column) with k
+// contiguous.  M is cut into 16 x 32 blocks of 1 KB; block (rb, kb) starts at
+// element (kb (n/16) + rb) 512, so the BM x 32 k-slab that a workgroup loads
+// per k-chunk is BM/16 consecutive KB.  Inside a block, row rr's 16-byte
+// chunk c (k = 8c .. 8c+7) sits at rr 32 + 8 (c ^ swz(rr)) with
+// swz(rr) = ((rr >> 1) ^ (rr >> 3)) & 3: the sixteen (or eight) lanes that
+// one LDS cycle serves for an MFMA fragment read -- consecutive rows, one
+// chunk -- then hit distinct banks on a 64-bank and on a 32-bank LDS.
+// Plane p of a split operand starts at element p n^2.
+#include "gemm_device.h"
+
+namespace ns {
+namespace dev {
+namespace {
+
+__device__ __forceinline__ int swz(int rr) { return ((rr >> 1) ^ (rr >> 3)) & 3; }
+
+// ---------------------------------------------------------------------------
+// FP32 matrix -> 16-bit panels.  One workgroup per 64 x 64 region of M: the
+// source is read with row-contiguous 16-byte loads (rows of X, or rows of Y
+// for the transposed Y^T), staged in LDS as M[r][k], then every 64 threads
+// write one 1 KB block contiguously.
+// ---------------------------------------------------------------------------
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void to_panels_kernel(const float* __restrict__ src, int n, int ld,
+                                                        int transpose, uint16_t* __restrict__ dst,
+                                                        const unsigned* __restrict__ amax) {
+  __shared__ float t[64][65];
+  const int r0 = 64 * blockIdx.y, k0 = 64 * blockIdx.x, tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int v = tid + 256 * i, a = v >> 4, c4 = (v & 15) * 4;
+    if (!transpose) {
+      const float4 x = *reinterpret_cast<const float4*>(src + (size_t)(r0 + a) * ld + k0 + c4);
+      t[a][c4] = x.x; t[a][c4 + 1] = x.y; t[a][c4 + 2] = x.z; t[a][c4 + 3] = x.w;
+    } else {   // src row k0 + a holds M[r0 + c4 ..][k0 + a]
+      const float4 x = *reinterpret_cast<const float4*>(src + (size_t)(k0 + a) * ld + r0 + c4);
+      t[c4][a] = x.x; t[c4 + 1][a] = x.y; t[c4 + 2][a] = x.z; t[c4 + 3][a] = x.w;
+    }
+  }
+  float scale = 1.f;
+  if constexpr (!SPLIT) {
+    const unsigned b = amax ? *amax : 0u;
+    const int e = b ? (int)((b >> 23) & 0xff) - 127 : 0;
+    scale = __int_as_float((14 - e + 127) << 23);
+  }
+  __syncthreads();
+  const size_t plane = (size_t)n * n;
+  const size_t nb16 = (size_t)(n / 16);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int q = tid + 256 * i;                  // chunk of the region: 8 blocks x 64
+    const int blk = q >> 6, pos = q & 63;
+    const int rbl = blk & 3, kbl = blk >> 2;
+    const int rr = pos >> 2, pc = pos & 3, c = pc ^ swz(rr);
+    const int r = 16 * rbl + rr, kk = 32 * kbl + 8 * c;
+    const size_t off = ((size_t)(k0 / 32 + kbl) * nb16 + (r0 / 16 + rbl)) * 512 + 8 * pos;
+    if constexpr (SPLIT) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = t[r][kk + e];
+        const __bf16 hb = (__bf16)x;
+        h[e] = hb;
+        l[e] = (__bf16)(x - (float)hb);
+      }
+      *reinterpret_cast<bf16x8*>(dst + off) = h;
+      *reinterpret_cast<bf16x8*>(dst + plane + off) = l;
+    } else {
+      f16x8 h;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) h[e] = (_Float16)(t[r][kk + e] * scale);
+      *reinterpret_cast<f16x8*>(dst + off) = h;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Product from panels.  NWM x NWN waves, each owning NI x NJ fragments of
+// v_mfma_f32_32x32x16_{bf16,f16}; k-chunk 32 (two MFMA k-steps), two LDS
+// stages.  Stage layout (16-bit elements): the X planes' BM/16 blocks, then
+// the Y planes' BN/16 blocks -- the same bytes, in the same order, as the
+// global slabs, so every wave instruction of the loader copies one 1 KB block.
+// ---------------------------------------------------------------------------
+template <int NWM_, int NWN_, int NI_, int NJ_, bool SPLIT_>
+struct PolPanel {
+  static constexpr bool SPLIT = SPLIT_;
+  static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
+  static constexpr int WTM = 32 * NI, WTN = 32 * NJ;
+  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 32;
+  static constexpr int THREADS = 64 * NWM * NWN, NW = THREADS / 64;
+  static constexpr int PLANES = SPLIT ? 2 : 1;
+  static constexpr int A_BLK = PLANES * BM / 16, B_BLK = PLANES * BN / 16;   // 1 KB blocks
+  static constexpr int A_EL = A_BLK * 512, STAGE_EL = (A_BLK + B_BLK) * 512;
+  static constexpr int PER_WAVE = (A_BLK + B_BLK) / NW;
+  static_assert((A_BLK + B_BLK) % NW == 0, "loader blocks per wave");
+  static constexpr int CPITCH = BN + 4;                       // epilogue staging, floats
+  static constexpr int EPI_EL = WTM * CPITCH * 2;             // one wave-row, in 16-bit units
+  static constexpr int SMEM_EL = 2 * STAGE_EL > EPI_EL ? 2 * STAGE_EL : EPI_EL;
+};
+
+template <class Q>
+__global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs args) {
+  __shared__ __align__(16) uint16_t smem[Q::SMEM_EL];
+  const int n = args.n;
+  const int tiles_m = n / Q::BM, tiles_n = n / Q::BN;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int row0 = tm * Q::BM, col0 = tn * Q::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / Q::NWN, wn = wave % Q::NWN;
+  const uint16_t* __restrict__ Xp = static_cast<const uint16_t*>(args.X);
+  const uint16_t* __restrict__ Yp = static_cast<const uint16_t*>(args.Y);
+  const size_t plane = (size_t)n * n;
+  const size_t chunk_el = (size_t)n * 32;          // one k-slab of 32: n/16 blocks of 512
+
+  // loader: this wave's blocks; element offsets within a k-slab (plane
+  // included) and LDS offsets within a stage, both per lane
+  uint32_t goff[Q::PER_WAVE];
+  const uint16_t* gsrc[Q::PER_WAVE];
+  int loff[Q::PER_WAVE];
+#pragma unroll
+  for (int i = 0; i < Q::PER_WAVE; ++i) {
+    const int b = wave + i * Q::NW;
+    if (b < Q::A_BLK) {
+      const int p = b / (Q::BM / 16), rb = b % (Q::BM / 16);
+      gsrc[i] = Xp + (size_t)p * plane;
+      goff[i] = (uint32_t)((row0 / 16 + rb) * 512 + 8 * lane);
+    } else {
+      const int bb = b - Q::A_BLK;
+      const int p = bb / (Q::BN / 16), cb = bb % (Q::BN / 16);
+      gsrc[i] = Yp + (size_t)p * plane;
+      goff[i] = (uint32_t)((col0 / 16 + cb) * 512 + 8 * lane);
+    }
+    loff[i] = b * 512;
+  }
+  auto issue = [&](int kc, int stage) {
+    const size_t kofs = (size_t)kc * chunk_el;
+#pragma unroll
+    for (int i = 0; i < Q::PER_WAVE; ++i)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(gsrc[i] + kofs + goff[i]),
+          (__attribute__((address_space(3))) void*)(smem + stage * Q::STAGE_EL + loff[i]), 16, 0, 0);
+  };
+
+  // fragment reads: lane l takes row (l & 31) of a 32-row fragment and chunk
+  // 2 ks + (l >> 5); the row's block and swizzle depend on the lane only
+  const int fr = lane & 31, rr = fr & 15;
+  const int lrow = (fr >> 4) * 512 + rr * 32;
+  const int cofs0 = 8 * ((lane >> 5) ^ swz(rr));           // ks = 0
+  const int cofs1 = 8 * ((2 + (lane >> 5)) ^ swz(rr));     // ks = 1
+
+  f32x16 acc[Q::NI][Q::NJ];
+#pragma unroll
+  for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+    for (int j = 0; j < Q::NJ; ++j) acc[i][j] = f32x16{};
+
+  const int nk = n / Q::BK;
+  issue(0, 0);
+  wait_vmcnt<0>();
+  __syncthreads();
+  int cur = 0;
+  for (int kc = 0; kc < nk; ++kc) {
+    if (kc + 1 < nk) issue(kc + 1, cur ^ 1);
+    const uint16_t* As = smem + cur * Q::STAGE_EL;
+    const uint16_t* Bs = As + Q::A_EL;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int co = ks ? cofs1 : cofs0;
+      u16x8 ah[Q::NI], al[Q::NI], bh[Q::NJ], bl[Q::NJ];
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i) {
+        const int off = (wm * Q::WTM / 16 + 2 * i) * 512 + lrow + co;
+        ah[i] = *reinterpret_cast<const u16x8*>(As + off);
+        if constexpr (Q::SPLIT) al[i] = *reinterpret_cast<const u16x8*>(As + Q::BM * 32 + off);
+      }
+#pragma unroll
+      for (int j = 0; j < Q::NJ; ++j) {
+        const int off = (wn * Q::WTN / 16 + 2 * j) * 512 + lrow + co;
+        bh[j] = *reinterpret_cast<const u16x8*>(Bs + off);
+        if constexpr (Q::SPLIT) bl[j] = *reinterpret_cast<const u16x8*>(Bs + Q::BN * 32 + off);
+      }
+      if constexpr (Q::SPLIT) {
+        // the three partial products in turn over all fragments, so that
+        // consecutive MFMAs never wait on each other's accumulator
+#pragma unroll
+        for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+          for (int j = 0; j < Q::NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al[i]),
+                                                                __builtin_bit_cast(bf16x8, bh[j]),
+                                                                acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+          for (int j = 0; j < Q::NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                                __builtin_bit_cast(bf16x8, bl[j]),
+                                                                acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+          for (int j = 0; j < Q::NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                                __builtin_bit_cast(bf16x8, bh[j]),
+                                                                acc[i][j], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+          for (int j = 0; j < Q::NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, ah[i]),
+                                                               __builtin_bit_cast(f16x8, bh[j]),
+                                                               acc[i][j], 0, 0, 0);
+      }
+    }
+    // chunk kc + 1 must be in LDS, and every wave done with chunk kc, before
+    // the next iteration overwrites this stage
+    wait_vmcnt<0>();
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // epilogue: stage one wave-row of FP32 results at a time, then apply the
+  // affine outputs with row-contiguous 16-byte vectors
+  const GemmParams& p = *args.epi;
+  float unscale = 1.f;
+  if constexpr (!Q::SPLIT) {
+    const int ex = amax_exponent(p.xamax), ey = amax_exponent(p.yamax);
+    unscale = pow2f(ex - 14) * pow2f(ey - 14);
+  }
+  const bool f32_out = all_f32(p);
+  float* C = reinterpret_cast<float*>(smem);
+  constexpr int VEC = 4, VPR = Q::BN / VEC;
+  EpiState st{0.0, 0.f, 0};
+#pragma unroll 1
+  for (int pass = 0; pass < Q::NWM; ++pass) {
+    if (wm == pass) {
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+        for (int j = 0; j < Q::NJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            C[(32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * Q::CPITCH + wn * Q::WTN + 32 * j +
+              (lane & 31)] = acc[i][j][r] * unscale;
+    }
+    __syncthreads();
+    for (int v = tid; v < Q::WTM * VPR; v += Q::THREADS) {
+      const int r = v / VPR, cv = (v % VPR) * VEC;
+      double c[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e];
+      if (f32_out) epi_vec_f32<VEC>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
+      else epi_vec<VEC>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
+    }
+    __syncthreads();
+  }
+  publish_stats<Q::THREADS>(p, st, reinterpret_cast<double*>(smem));
+}
+
+using BF3Panel = PolPanel<2, 4, 4, 2, true>;    // 256 x 256 tile, 8 waves of 128 x 64
+using H16Panel = PolPanel<2, 4, 4, 2, false>;
+
+template <class Q>
+hipError_t launch_panel(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
+  if (host.n % Q::BM || host.n % Q::BN || host.ld != host.n) return hipErrorInvalidValue;
+  const int grid = (host.n / Q::BM) * (host.n / Q::BN);
+  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
+  hipLaunchKernelGGL(gemm_panel_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace dev
+
+bool panel_path(Engine e, int n) {
+  return (e == ENG_BF16X3 || e == ENG_F16S) && n >= kPanelMin && n % 256 == 0;
+}
+
+size_t panel_bytes(Engine e, int n) {
+  return (size_t)(e == ENG_BF16X3 ? 2 : 1) * n * n * sizeof(uint16_t);
+}
+
+hipError_t launch_to_panels(Engine e, const float* src, int n, int ld, int transpose, void* dst,
+                            const unsigned* amax, hipStream_t s) {
+  if (n % 64 || ld < n) return hipErrorInvalidValue;
+  const dim3 grid(n / 64, n / 64);
+  if (e == ENG_BF16X3)
+    hipLaunchKernelGGL(dev::to_panels_kernel<true>, grid, dim3(256), 0, s, src, n, ld, transpose,
+                       static_cast<uint16_t*>(dst), amax);
+  else if (e == ENG_F16S)
+    hipLaunchKernelGGL(dev::to_panels_kernel<false>, grid, dim3(256), 0, s, src, n, ld, transpose,
+                       static_cast<uint16_t*>(dst), amax);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_panels(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s) {
+  switch (e) {
+    case ENG_BF16X3: return dev::launch_panel<dev::BF3Panel>(host, dev, s);
+    case ENG_F16S: return dev::launch_panel<dev::H16Panel>(host, dev, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ns

@@ -81,3 +81,19 @@ def test_residual_form_corrects_low_precision(ns):
     e_t, e_r = series.rel_fro(tele, ref), series.rel_fro(resid, ref)
     say(f"   telescoping {e_t:.3e}  residual {e_r:.3e}")
     assert e_r < e_t / 10
+
+
+@pytest.mark.parametrize("dtype", ["f32_acc64", "split_bf16", "f16_scaled"])
+@pytest.mark.parametrize("method", ["radix9", "radix9_resid"])
+@pytest.mark.parametrize("n", [300, 2048])
+def test_mixed_precision_nonsymmetric(ns, method, dtype, n):
+    """A nonsymmetric input: every product X Y of the schedule differs from
+    X Y^T, so a row/column mix-up of either operand (n = 2048 runs the
+    16-bit panel engines, whose Y operand is laid out by columns) fails."""
+    g = workloads.gaussian(n, 0.5, 300 + n)
+    got, rep = run(ns, g.A, 81, method, dtype)
+    ref, orep = series.evaluate(g.A, 81, method)
+    err = series.rel_fro(got, ref)
+    say(f"   rel err {err:.3e}")
+    assert err < TOL[dtype]
+    assert rep["gemms_performed"] == orep["products"]
