@@ -18,6 +18,7 @@ struct EpiOut {
   double a;
   double z[kMaxZ];
   double id;
+  unsigned* amax;            // scaled-FP16 products: atomicMax of |out| as float bits, or null
 };
 
 // Operand storage / arithmetic of a product launch.
@@ -43,7 +44,8 @@ struct GemmParams {
   EpiOut out[kMaxOut];
   double* sumsq;              // if non-null: += sum of squares of output 0
   int* nonfinite;             // if non-null: set to 1 if any output 0 entry is Inf/NaN
-  unsigned* amax;             // if non-null: atomicMax of |output 0| as float bits
+  unsigned* amax;             // if non-null: atomicMax of |output 0| as float bits (the scaled-FP16
+                              // products use the per-output EpiOut::amax instead)
   const unsigned* xamax;      // low-precision engines: max-abs of X (float bits) for scaling
   const unsigned* yamax;      // ... of Y
 };

@@ -37,11 +37,22 @@ __device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, i
 // ---------------------------------------------------------------------------
 // epilogue
 // ---------------------------------------------------------------------------
-struct EpiState {
+// Per-thread epilogue statistics; the AMAXO form also tracks every output's
+// max-abs (scaled-FP16 products only, so the other kernels carry no extra state).
+template <bool AMAXO>
+struct EpiStateT {
   double ssq;
   float amax;
   int bad;
 };
+template <>
+struct EpiStateT<true> {
+  double ssq;
+  float amax;
+  int bad;
+  float oamax[kMaxOut];
+};
+using EpiState = EpiStateT<false>;
 
 // Load / store VEC consecutive elements of a row-major matrix at idx as
 // doubles; `f64` selects the element type.  idx is a multiple of VEC, so the
@@ -88,9 +99,9 @@ __device__ __forceinline__ void store_vec(void* p, int f64, size_t idx, double (
 // Apply the affine epilogue to VEC consecutive product values c[] at
 // (row, col .. col + VEC - 1).  Every loop has a compile-time trip count so
 // the kernel-argument struct is only ever indexed statically.
-template <int VEC>
+template <int VEC, bool AMAXO = false>
 __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, const double (&c)[VEC],
-                                        EpiState& st) {
+                                        EpiStateT<AMAXO>& st) {
   const size_t idx = (size_t)row * p.ld + col;
   double z[kMaxZ][VEC];
 #pragma unroll
@@ -112,6 +123,10 @@ __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, c
       for (int i = 0; i < kMaxZ; ++i) y[t] += e.z[i] * z[i][t];
     }
     store_vec<VEC>(e.ptr, e.f64, idx, y);
+    if constexpr (AMAXO) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) st.oamax[o] = fmaxf(st.oamax[o], (float)fabs(y[t]));
+    }
     if (o == 0) {
 #pragma unroll
       for (int t = 0; t < VEC; ++t) {
@@ -127,9 +142,9 @@ __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, c
 // arithmetic, no per-element type branches (fewer registers; used by the FP32
 // engine whenever a product's inputs and outputs are all FP32, and always by
 // the batched kernel, so both produce identical bits).
-template <int VEC>
+template <int VEC, bool AMAXO = false>
 __device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int col,
-                                            const double (&c)[VEC], EpiState& st) {
+                                            const double (&c)[VEC], EpiStateT<AMAXO>& st) {
   static_assert(VEC == 4, "float epilogue works on float4 vectors");
   const size_t idx = (size_t)row * p.ld + col;
   float z[kMaxZ][VEC];
@@ -159,6 +174,10 @@ __device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int co
       for (int i = 0; i < kMaxZ; ++i) y[t] += zc[i] * z[i][t];
     }
     *reinterpret_cast<float4*>(static_cast<float*>(e.ptr) + idx) = make_float4(y[0], y[1], y[2], y[3]);
+    if constexpr (AMAXO) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) st.oamax[o] = fmaxf(st.oamax[o], fabsf(y[t]));
+    }
     if (o == 0) {
 #pragma unroll
       for (int t = 0; t < VEC; ++t) {
@@ -183,23 +202,32 @@ __device__ __forceinline__ bool all_f32(const GemmParams& p) {
 }
 
 // Reduce the per-thread statistics over the workgroup and publish them with
-// one atomic each.  `scratch` is LDS of at least 3 * (THREADS / 64) doubles;
-// the caller synchronises before the call.
-template <int THREADS>
-__device__ __forceinline__ void publish_stats(const GemmParams& p, EpiState st, double* scratch) {
-  if (!p.sumsq && !p.nonfinite && !p.amax) return;
+// one atomic each.  `scratch` is LDS of at least (3 + kMaxOut) * (THREADS / 64)
+// doubles; the caller synchronises before the call.  AMAXO also publishes the
+// per-output max-abs to EpiOut::amax.
+template <int THREADS, bool AMAXO = false>
+__device__ __forceinline__ void publish_stats(const GemmParams& p, EpiStateT<AMAXO> st, double* scratch) {
+  if (!AMAXO && !p.sumsq && !p.nonfinite && !p.amax) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     st.ssq += __shfl_xor(st.ssq, off);
     st.amax = fmaxf(st.amax, __shfl_xor(st.amax, off));
     st.bad |= __shfl_xor(st.bad, off);
+    if constexpr (AMAXO) {
+#pragma unroll
+      for (int o = 0; o < kMaxOut; ++o) st.oamax[o] = fmaxf(st.oamax[o], __shfl_xor(st.oamax[o], off));
+    }
   }
   constexpr int NW = THREADS / 64;
   if (lane == 0) {
     scratch[wave] = st.ssq;
     scratch[NW + wave] = (double)st.amax;
     scratch[2 * NW + wave] = (double)st.bad;
+    if constexpr (AMAXO) {
+#pragma unroll
+      for (int o = 0; o < kMaxOut; ++o) scratch[(3 + o) * NW + wave] = (double)st.oamax[o];
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -212,6 +240,14 @@ __device__ __forceinline__ void publish_stats(const GemmParams& p, EpiState st, 
     if (p.sumsq) atomicAdd(p.sumsq, s);
     if (p.nonfinite && b != 0.0) atomicOr(p.nonfinite, 1);
     if (p.amax) atomicMax(p.amax, __float_as_uint((float)a));
+    if constexpr (AMAXO) {
+      for (int o = 0; o < kMaxOut; ++o) {
+        if (o >= p.no || !p.out[o].amax) continue;
+        double m = 0.0;
+        for (int w = 0; w < NW; ++w) m = fmax(m, scratch[(3 + o) * NW + w]);
+        atomicMax(p.out[o].amax, __float_as_uint((float)m));
+      }
+    }
   }
 }
 
@@ -833,7 +869,7 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs ar
   const GemmParams& p = *args.epi;
   float* C = reinterpret_cast<float*>(smem);
   constexpr int VEC = 4, VPR = Q::BN / VEC;
-  EpiState st{0.0, 0.f, 0};
+  EpiStateT<!Q::SPLIT> st{};
 #pragma unroll 1
   for (int pass = 0; pass < Q::NWM; ++pass) {
     if (wm == pass) {
@@ -852,11 +888,11 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs ar
       double c[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
-      epi_vec<VEC>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
+      epi_vec<VEC, !Q::SPLIT>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
     }
     __syncthreads();
   }
-  publish_stats<Q::THREADS>(p, st, reinterpret_cast<double*>(smem));
+  publish_stats<Q::THREADS, !Q::SPLIT>(p, st, reinterpret_cast<double*>(smem));
 }
 
 }  // namespace dev

@@ -337,11 +337,23 @@ struct Ctx {
     p.sumsq = norm_level >= 0 ? &scal->level_sumsq[norm_level] : nullptr;
     p.nonfinite = &scal->nonfinite;
     if (eng == ENG_F16S) {
-      // the scaled-FP16 engine needs each operand's max-abs: the epilogue
-      // records it for output 0, a separate pass for the other outputs
-      p.amax = new_amax_slot();
+      // the scaled-FP16 engine needs each operand's max-abs.  Its own
+      // products record it for every FP32 output in the epilogue; an FP64
+      // product (the residual) for output 0, with a separate pass for others.
       p.xamax = X.amax;
       p.yamax = Y.amax;
+      if (e == ENG_F16S) {
+        int k = 0;
+        for (const Out& o : outs) {
+          if (!o.b->f64) {
+            p.out[k].amax = new_amax_slot();
+            o.b->amax = p.out[k].amax;
+          }
+          ++k;
+        }
+      } else {
+        p.amax = new_amax_slot();
+      }
     }
     ops.push_back(op);
     ++gemms;

@@ -94,30 +94,39 @@ __global__ __launch_bounds__(256) void to_panels_kernel(const float* __restrict_
 
 // ---------------------------------------------------------------------------
 // Product from panels.  NWM x NWN waves, each owning NI x NJ fragments of
-// v_mfma_f32_32x32x16_{bf16,f16}; k-chunk 32 (two MFMA k-steps), two LDS
-// stages.  Stage layout (16-bit elements): the X planes' BM/16 blocks, then
-// the Y planes' BN/16 blocks -- the same bytes, in the same order, as the
-// global slabs, so every wave instruction of the loader copies one 1 KB block.
+// v_mfma_f32_32x32x16_{bf16,f16}; k-chunk 32 KSLAB (two MFMA k-steps per
+// 32-slab), STAGES LDS stages (prefetch distance STAGES - 1).  The epilogue
+// stages EFR fragment-rows (32 EFR output rows) per pass.  Stage layout
+// (16-bit elements), per slab: the X
+// planes' BM/16 blocks, then the Y planes' BN/16 blocks -- the same bytes, in
+// the same order, as the global slabs, so every wave instruction of the
+// loader copies one 1 KB block.
 // ---------------------------------------------------------------------------
-template <int NWM_, int NWN_, int NI_, int NJ_, bool SPLIT_>
+template <int NWM_, int NWN_, int NI_, int NJ_, bool SPLIT_, int KSLAB_, int STAGES_, int EFR_,
+          int MINB_ = 1>
 struct PolPanel {
+  static constexpr int MINB = MINB_;                          // workgroups per CU to fit
   static constexpr bool SPLIT = SPLIT_;
-  static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
+  static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_, KSLAB = KSLAB_;
+  static constexpr int STAGES = STAGES_, EFR = EFR_;
+  static_assert(STAGES == 2 || STAGES == 3, "two or three LDS stages");
+  static_assert(NI % EFR == 0, "epilogue passes");
   static constexpr int WTM = 32 * NI, WTN = 32 * NJ;
-  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 32;
+  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 32 * KSLAB;
   static constexpr int THREADS = 64 * NWM * NWN, NW = THREADS / 64;
   static constexpr int PLANES = SPLIT ? 2 : 1;
   static constexpr int A_BLK = PLANES * BM / 16, B_BLK = PLANES * BN / 16;   // 1 KB blocks
-  static constexpr int A_EL = A_BLK * 512, STAGE_EL = (A_BLK + B_BLK) * 512;
-  static constexpr int PER_WAVE = (A_BLK + B_BLK) / NW;
-  static_assert((A_BLK + B_BLK) % NW == 0, "loader blocks per wave");
+  static constexpr int A_EL = A_BLK * 512, SLAB_EL = (A_BLK + B_BLK) * 512;
+  static constexpr int STAGE_EL = KSLAB * SLAB_EL;
+  static constexpr int PER_WAVE = KSLAB * (A_BLK + B_BLK) / NW;
+  static_assert((KSLAB * (A_BLK + B_BLK)) % NW == 0, "loader blocks per wave");
   static constexpr int CPITCH = BN + 4;                       // epilogue staging, floats
-  static constexpr int EPI_EL = WTM * CPITCH * 2;             // one wave-row, in 16-bit units
-  static constexpr int SMEM_EL = 2 * STAGE_EL > EPI_EL ? 2 * STAGE_EL : EPI_EL;
+  static constexpr int EPI_EL = 32 * EFR * CPITCH * 2;       // one pass, in 16-bit units
+  static constexpr int SMEM_EL = STAGES * STAGE_EL > EPI_EL ? STAGES * STAGE_EL : EPI_EL;
 };
 
 template <class Q>
-__global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs args) {
+__global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_panel_kernel(const MainArgs args) {
   __shared__ __align__(16) uint16_t smem[Q::SMEM_EL];
   const int n = args.n;
   const int tiles_m = n / Q::BM, tiles_n = n / Q::BN;
@@ -129,7 +138,7 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs a
   const uint16_t* __restrict__ Xp = static_cast<const uint16_t*>(args.X);
   const uint16_t* __restrict__ Yp = static_cast<const uint16_t*>(args.Y);
   const size_t plane = (size_t)n * n;
-  const size_t chunk_el = (size_t)n * 32;          // one k-slab of 32: n/16 blocks of 512
+  const size_t chunk_el = (size_t)n * Q::BK;      // one k-chunk: KSLAB slabs of n/16 blocks
 
   // loader: this wave's blocks; element offsets within a k-slab (plane
   // included) and LDS offsets within a stage, both per lane
@@ -139,15 +148,16 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs a
 #pragma unroll
   for (int i = 0; i < Q::PER_WAVE; ++i) {
     const int b = wave + i * Q::NW;
-    if (b < Q::A_BLK) {
-      const int p = b / (Q::BM / 16), rb = b % (Q::BM / 16);
+    const int slab = b / (Q::A_BLK + Q::B_BLK), bs = b % (Q::A_BLK + Q::B_BLK);
+    if (bs < Q::A_BLK) {
+      const int p = bs / (Q::BM / 16), rb = bs % (Q::BM / 16);
       gsrc[i] = Xp + (size_t)p * plane;
-      goff[i] = (uint32_t)((row0 / 16 + rb) * 512 + 8 * lane);
+      goff[i] = (uint32_t)(slab * n * 32 + (row0 / 16 + rb) * 512 + 8 * lane);
     } else {
-      const int bb = b - Q::A_BLK;
+      const int bb = bs - Q::A_BLK;
       const int p = bb / (Q::BN / 16), cb = bb % (Q::BN / 16);
       gsrc[i] = Yp + (size_t)p * plane;
-      goff[i] = (uint32_t)((col0 / 16 + cb) * 512 + 8 * lane);
+      goff[i] = (uint32_t)(slab * n * 32 + (col0 / 16 + cb) * 512 + 8 * lane);
     }
     loff[i] = b * 512;
   }
@@ -174,16 +184,30 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs a
     for (int j = 0; j < Q::NJ; ++j) acc[i][j] = f32x16{};
 
   const int nk = n / Q::BK;
+  constexpr int S = Q::STAGES;
   issue(0, 0);
-  wait_vmcnt<0>();
+  if constexpr (S == 3) {
+    if (nk > 1) {
+      issue(1, 1);
+      wait_vmcnt<Q::PER_WAVE>();     // chunk 0 landed, chunk 1 may still fly
+    } else {
+      wait_vmcnt<0>();
+    }
+  } else {
+    wait_vmcnt<0>();
+  }
   __syncthreads();
   int cur = 0;
   for (int kc = 0; kc < nk; ++kc) {
-    if (kc + 1 < nk) issue(kc + 1, cur ^ 1);
-    const uint16_t* As = smem + cur * Q::STAGE_EL;
-    const uint16_t* Bs = As + Q::A_EL;
+    // the stage of chunk kc + S - 1 was last read in iteration kc - 1, which
+    // every wave has finished (barrier at its end)
+    const int nxt = kc + S - 1;
+    if (nxt < nk) issue(nxt, cur == 0 ? S - 1 : cur - 1);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int kk = 0; kk < 2 * Q::KSLAB; ++kk) {
+      const int ks = kk & 1;
+      const uint16_t* As = smem + cur * Q::STAGE_EL + (kk >> 1) * Q::SLAB_EL;
+      const uint16_t* Bs = As + Q::A_EL;
       const int co = ks ? cofs1 : cofs0;
       u16x8 ah[Q::NI], al[Q::NI], bh[Q::NJ], bl[Q::NJ];
 #pragma unroll
@@ -233,14 +257,19 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs a
       }
     }
     // chunk kc + 1 must be in LDS, and every wave done with chunk kc, before
-    // the next iteration overwrites this stage
-    wait_vmcnt<0>();
+    // the next iteration overwrites this stage; newer loads may stay in flight
+    if constexpr (S == 3) {
+      if (nxt < nk) wait_vmcnt<Q::PER_WAVE>();
+      else wait_vmcnt<0>();
+    } else {
+      wait_vmcnt<0>();
+    }
     __syncthreads();
-    cur ^= 1;
+    cur = cur + 1 == S ? 0 : cur + 1;
   }
 
-  // epilogue: stage one wave-row of FP32 results at a time, then apply the
-  // affine outputs with row-contiguous 16-byte vectors
+  // epilogue: stage EFR fragment-rows of FP32 results at a time, then apply
+  // the affine outputs with row-contiguous 16-byte vectors
   const GemmParams& p = *args.epi;
   float unscale = 1.f;
   if constexpr (!Q::SPLIT) {
@@ -250,35 +279,41 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_panel_kernel(const MainArgs a
   const bool f32_out = all_f32(p);
   float* C = reinterpret_cast<float*>(smem);
   constexpr int VEC = 4, VPR = Q::BN / VEC;
-  EpiState st{0.0, 0.f, 0};
+  EpiStateT<!Q::SPLIT> st{};
+  constexpr int PPW = Q::NI / Q::EFR;                // passes per wave-row
+  constexpr int PROWS = 32 * Q::EFR;
 #pragma unroll 1
-  for (int pass = 0; pass < Q::NWM; ++pass) {
-    if (wm == pass) {
+  for (int pass = 0; pass < Q::NWM * PPW; ++pass) {
+    const int pw = pass / PPW, pi = pass % PPW;
+    if (wm == pw) {
 #pragma unroll
-      for (int i = 0; i < Q::NI; ++i)
+      for (int i = 0; i < Q::NI; ++i) {
+        if (i / Q::EFR != pi) continue;
 #pragma unroll
         for (int j = 0; j < Q::NJ; ++j)
 #pragma unroll
           for (int r = 0; r < 16; ++r)
-            C[(32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * Q::CPITCH + wn * Q::WTN + 32 * j +
-              (lane & 31)] = acc[i][j][r] * unscale;
+            C[(32 * (i % Q::EFR) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * Q::CPITCH + wn * Q::WTN +
+              32 * j + (lane & 31)] = acc[i][j][r] * unscale;
+      }
     }
     __syncthreads();
-    for (int v = tid; v < Q::WTM * VPR; v += Q::THREADS) {
+    const int grow = row0 + pw * Q::WTM + pi * PROWS;
+    for (int v = tid; v < PROWS * VPR; v += Q::THREADS) {
       const int r = v / VPR, cv = (v % VPR) * VEC;
       double c[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e];
-      if (f32_out) epi_vec_f32<VEC>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
-      else epi_vec<VEC>(p, row0 + pass * Q::WTM + r, col0 + cv, c, st);
+      if (f32_out) epi_vec_f32<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
+      else epi_vec<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
     }
     __syncthreads();
   }
-  publish_stats<Q::THREADS>(p, st, reinterpret_cast<double*>(smem));
+  publish_stats<Q::THREADS, !Q::SPLIT>(p, st, reinterpret_cast<double*>(smem));
 }
 
-using BF3Panel = PolPanel<2, 4, 4, 2, true>;    // 256 x 256 tile, 8 waves of 128 x 64
-using H16Panel = PolPanel<2, 4, 4, 2, false>;
+using BF3Panel = PolPanel<2, 4, 4, 2, true, 1, 2, 4>;    // 256 x 256 tile, 8 waves of 128 x 64
+using H16Panel = PolPanel<2, 4, 4, 2, false, 1, 2, 4>;
 
 template <class Q>
 hipError_t launch_panel(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
