@@ -10,7 +10,8 @@ blocking, fusion or reordering beyond what the paper's steps state.
 
 Schedules round k up to the smallest pure power of the radix, k_eff >= k,
 because the paper evaluates only k = m^t (Sec. 6, setup); the report carries
-k_eff.  Product counts follow the literal schedules, including the product
+k_eff.  The exception is ``mixed``, which evaluates S_k for any k exactly by
+combining radix updates with the additive split of the series.  Product counts follow the literal schedules, including the product
 with S_1 = I and the last power or residual update, which is how the paper's
 Table 2 counts them.
 """
@@ -93,14 +94,83 @@ def plan(k: int, method: str) -> Tuple[int, int, int]:
 
     naive: k - 1 products (Sec. 2.1).  Radix-m methods: t = ceil(log_m k)
     levels of mu_m + 2 products each (Sec. 2.2 cost model, Sec. 5.4).
+    mixed: k exactly; levels counts its radix updates.
     """
     if k < 1:
         raise ValueError("k must be >= 1")
     if method == "naive":
         return k, k - 1, k - 1
+    if method == "mixed":
+        products, steps = mixed_plan(k)
+        return k, sum(1 for s in steps if s > 1), products
     m = RADIX[method]
     t = _levels(k, m)
     return m ** t, t, PER_LEVEL[method] * t
+
+
+# ---------------------------------------------------------------------------
+# exact S_k for any k: radix updates and the additive step
+# ---------------------------------------------------------------------------
+# A radix-m update (S_n, A^n) -> (S_mn, A^mn) costs mu_m + 2 products with an
+# exact kernel: binary (mu_2 = 0, T_2 = I + B), ternary (mu_3 = 1), quinary
+# (mu_5 = 2, Sec. 2.3) and radix-9 (mu_9 = 3, Thm 3.1).  The additive step
+# (S_n, A^n) -> (S_{n+1}, A^{n+1}) takes the series split at n,
+# S_{n+r} = S_n + A^n S_r, with r = 1 (S_1 = I), so S_{n+1} = S_n + A^n, and
+# A^{n+1} = A A^n: one product.  When the additive step is the last step and
+# a product came before it, it needs no new power and costs nothing (the sum
+# rides on the previous product).  With nothing before it (k = 2) it is
+# counted as one product.
+
+MIXED_COST = {9: 5, 5: 4, 3: 3, 2: 2}
+
+
+def _mixed_best(n: int, memo: Dict[int, Tuple[int, int]]) -> Tuple[int, int]:
+    """(products, choice) to reach (S_n, A^n) from (S_1, A^1) = (I, A).
+    choice 0: n - 1 additive steps from 1; choice m: reach n // m, one
+    radix-m update, then n % m additive steps.  (Additive steps after a
+    radix-m update are fewer than m in an optimal plan: m of them cost more
+    than one additive step before the update.)  Ties keep the earlier
+    option, in the order: additive chain, m = 9, 5, 3, 2."""
+    if n in memo:
+        return memo[n]
+    best = (n - 1, 0)
+    for m in (9, 5, 3, 2):
+        if n >= m:
+            c = _mixed_best(n // m, memo)[0] + MIXED_COST[m] + n % m
+            if c < best[0]:
+                best = (c, m)
+    memo[n] = best
+    return best
+
+
+def _mixed_steps(n: int, memo) -> List[int]:
+    choice = _mixed_best(n, memo)[1]
+    if choice == 0:
+        return [1] * (n - 1)
+    return _mixed_steps(n // choice, memo) + [choice] + [1] * (n % choice)
+
+
+def mixed_plan(k: int) -> Tuple[int, List[int]]:
+    """(products, steps) of the cheapest exact plan for S_k; a step is a
+    radix m in {2, 3, 5, 9} or 1 for the additive step.  The last additive
+    step is free after a product.  Same tie order as _mixed_best, with the
+    additive chain from 1 first."""
+    if k < 1:
+        raise ValueError("k must be >= 1")
+    if k == 1:
+        return 0, []
+    memo: Dict[int, Tuple[int, int]] = {}
+    best = (1 if k == 2 else k - 2, 0)
+    for m in (9, 5, 3, 2):
+        if k >= m:
+            r = k % m
+            c = _mixed_best(k // m, memo)[0] + MIXED_COST[m] + max(r - 1, 0)
+            if c < best[0]:
+                best = (c, m)
+    m = best[1]
+    if m == 0:
+        return best[0], [1] * (k - 1)
+    return best[0], _mixed_steps(k // m, memo) + [m] + [1] * (k % m)
 
 
 def lei_nakamura_count(k: int) -> int:
@@ -292,6 +362,46 @@ def hensel(A: np.ndarray, k: int):
     return general_radix(A, k, "hensel", kernel_hensel)
 
 
+def _kernel_exact(m: int, B: np.ndarray, mm: _Counter) -> np.ndarray:
+    """T_m(B) for the exact radices of the mixed schedule."""
+    I = _eye(B)
+    if m == 2:
+        return I + B
+    if m == 3:
+        return I + B + mm(B, B)
+    if m == 5:
+        return kernel_quinary(B, mm)
+    if m == 9:
+        return kernel_radix9(B, mm)
+    raise ValueError(f"no exact kernel for radix {m}")
+
+
+def mixed(A: np.ndarray, k: int):
+    """S_k(A) for any k, exactly (no round-up): the steps of mixed_plan from
+    (S_1, A^1) = (I, A).  A radix-m step is the Sec. 2.2 update
+    (S_mn = S_n T_m(A^n), A^mn = I - T + T A^n); an additive step is
+    S_{n+1} = S_n + A^n with A^{n+1} = A A^n, the last one without the power."""
+    products, steps = mixed_plan(k)
+    mm = _Counter()
+    I = _eye(A)
+    S, P = I.copy(), A.copy()
+    norms = []
+    for i, m in enumerate(steps):
+        last = i == len(steps) - 1
+        if m == 1:
+            if last and mm.n > 0:
+                S = S + P
+            else:
+                S, P = S + P, mm(A, P)
+        else:
+            T = _kernel_exact(m, P, mm)
+            S = mm(S, T)
+            P = I - T + mm(T, P)
+            norms.append(_fro(P))
+    assert mm.n == products
+    return S, _report("mixed", k, k, len(norms), mm, norms)
+
+
 SCHEDULES: Dict[str, Callable] = {
     "naive": naive_horner,
     "binary": binary,
@@ -302,6 +412,7 @@ SCHEDULES: Dict[str, Callable] = {
     "radix9_resid": radix9_resid,
     "quinary_resid": quinary_resid,
     "hensel": hensel,
+    "mixed": mixed,
 }
 
 

@@ -251,3 +251,78 @@ def test_residual_magnitudes_match_table4_in_distribution():
             assert printed / 5 < r < printed * 5, (method, k, r)
         else:
             assert r < 1e-12, (method, k, r)
+
+
+# --- exact S_k for any k (mixed radix with additive steps) ---------------------
+
+def test_mixed_equals_brute_force_for_every_k_bit_for_bit(rational3):
+    """mixed gives S_k itself, not S_k_eff: every k from 1 to 60 and a few
+    beyond, in exact rational arithmetic against explicit powers.  A wrong
+    index in the additive step (S_n + A^(n+1)) or a dropped final step fails."""
+    P = rational3.copy()
+    powers = [series._eye(rational3)]
+    for _ in range(130):
+        powers.append(powers[-1] @ rational3)
+    prefix = [powers[0]]
+    for j in range(1, 130):
+        prefix.append(prefix[-1] + powers[j])
+    for k in list(range(1, 61)) + [81, 82, 100, 127, 128]:
+        S, rep = series.mixed(P, k)
+        assert (S == prefix[k - 1]).all(), k
+        assert rep["k_eff"] == k
+
+
+def _dijkstra_costs(K):
+    """Independent optimum: shortest paths over n = 1..K with edges n -> m n
+    (cost mu_m + 2 for the exact kernels) and n -> n + 1 (cost 1); the final
+    additive step is free after at least one product."""
+    import heapq
+    cost = {2: 2, 3: 3, 5: 4, 9: 5}
+    dist = [math.inf] * (K + 1)
+    dist[1] = 0
+    heap = [(0, 1)]
+    while heap:
+        d, n = heapq.heappop(heap)
+        if d > dist[n]:
+            continue
+        edges = [(n + 1, 1)] + [(n * m, c) for m, c in cost.items()]
+        for v, c in edges:
+            if v <= K and d + c < dist[v]:
+                dist[v] = d + c
+                heapq.heappush(heap, (d + c, v))
+    final = {1: 0}
+    for k in range(2, K + 1):
+        free_last = dist[k - 1] if k - 1 >= 2 else dist[k - 1] + 1
+        final[k] = min(dist[k], free_last)
+    return final
+
+
+def test_mixed_plan_is_optimal_against_shortest_paths():
+    K = 3000
+    ref = _dijkstra_costs(K)
+    for k in range(1, K + 1):
+        products, steps = series.mixed_plan(k)
+        assert products == ref[k], k
+        # the plan reaches k: replay it
+        n = 1
+        for s in steps:
+            n = n + 1 if s == 1 else n * s
+        assert n == k
+
+
+def test_mixed_never_costs_more_than_the_pure_radices_at_their_own_k():
+    for m, method in ((2, "binary"), (3, "ternary"), (5, "quinary"), (9, "radix9")):
+        for t in range(1, 8):
+            k = m ** t
+            assert series.mixed_plan(k)[0] <= series.plan(k, method)[2], (method, k)
+    # k = 3375 = 15^3: exact S_3375 in fewer products than radix-9 (k_eff 6561)
+    assert series.mixed_plan(3375)[0] < series.plan(3375, "radix9")[2]
+
+
+def test_mixed_closed_form_large_k():
+    w = workloads.symmetric(40, 0.97, 11)
+    for k in (1000, 3375, 4097, 12345):
+        S, rep = series.mixed(w.A, k)
+        ref = series.closed_form(w.A, k)
+        assert series.rel_fro(S, ref) < 1e-12, k
+        assert rep["products"] == series.mixed_plan(k)[0]
