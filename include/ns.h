@@ -24,7 +24,8 @@
  *     ns_report.nonfinite and in the growth of ns_report.level_norm.
  *   - k is rounded up to k_eff, the smallest pure power of the method's radix
  *     (the paper evaluates pure powers k = m^t only, Sec. 6); k_eff is
- *     reported.  NS_NAIVE uses k itself.  k = 1 gives I with no product.
+ *     reported.  NS_NAIVE and NS_MIXED use k itself.  k = 1 gives I with no
+ *     product.
  *   - One handle per host thread; calls that share a handle must not overlap.
  */
 #ifndef NS_H
@@ -65,7 +66,16 @@ enum ns_method {
   NS_TERNARY = 6,
   /* Hensel lifting, the m = 2 case of the framework (Sec. 5.5):
      Y <- Y (I + R), R <- I - (I - A) Y; 2 ceil(log2 k) products. */
-  NS_HENSEL = 7
+  NS_HENSEL = 7,
+  /* Exact S_k for any k, no round-up: the cheapest sequence of exact radix
+     updates (S_n, A^n) -> (S_mn, A^mn) (Sec. 2.2, kernels m = 2, 3, 5 and
+     the radix-9 kernel of Theorem 3.1, mu_m + 2 products each) and additive
+     steps S_{n+1} = S_n + A^n, A^{n+1} = A A^n (the split of the series at
+     n, one product).  A final additive step is fused into the previous
+     product's epilogue at no cost.  Ties between plans of equal cost go, in
+     order, to the additive chain from 1, then m = 9, 5, 3, 2 as the last
+     radix update.  levels counts the radix updates. */
+  NS_MIXED = 8
 };
 
 /* ---- compute precision ------------------------------------------------ */

@@ -16,10 +16,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libns.so")
 
 # methods (enum ns_method)
-NAIVE, BINARY, RADIX9, RADIX15, RADIX9_RESID, QUINARY, TERNARY, HENSEL = range(8)
+NAIVE, BINARY, RADIX9, RADIX15, RADIX9_RESID, QUINARY, TERNARY, HENSEL, MIXED = range(9)
 METHODS = {"naive": NAIVE, "binary": BINARY, "radix9": RADIX9, "radix15": RADIX15,
            "radix9_resid": RADIX9_RESID, "quinary": QUINARY, "ternary": TERNARY,
-           "hensel": HENSEL}
+           "hensel": HENSEL, "mixed": MIXED}
 # compute precision (enum ns_dtype)
 F64, F32, SPLIT_BF16, F16_SCALED, F32_ACC64 = range(5)
 DTYPES = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16, "f16_scaled": F16_SCALED,

@@ -23,6 +23,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ns.h"
@@ -143,8 +144,87 @@ int per_level(int method) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// exact plan for any k (NS_MIXED)
+// ---------------------------------------------------------------------------
+// Steps: m in {2, 3, 5, 9} is a radix-m update costing mu_m + 2 products; 1 is
+// an additive step costing one product (free when it is the last step and a
+// product came before it).  best(n) is the cheapest way from n = 1 to the pair
+// (S_n, A^n): either n - 1 additive steps, or best(n / m) + cost(m) + n % m
+// (an optimal plan never has m or more additive steps right after a radix-m
+// update: one additive step before the update replaces m after it).
+int mixed_cost(int m) { return m == 9 ? 5 : m == 5 ? 4 : m == 3 ? 3 : 2; }
+constexpr int kMixedRadices[4] = {9, 5, 3, 2};
+
+struct MixedBest {
+  std::unordered_map<int64_t, std::pair<int64_t, int>> memo;   // n -> (cost, choice)
+  std::pair<int64_t, int> best(int64_t n) {
+    auto it = memo.find(n);
+    if (it != memo.end()) return it->second;
+    std::pair<int64_t, int> b{n - 1, 0};
+    for (int m : kMixedRadices) {
+      if (n < m) continue;
+      const int64_t c = best(n / m).first + mixed_cost(m) + n % m;
+      if (c < b.first) b = {c, m};
+    }
+    memo.emplace(n, b);
+    return b;
+  }
+  void steps(int64_t n, std::vector<int>* out) {
+    const int m = best(n).second;
+    if (m == 0) {
+      out->insert(out->end(), (size_t)(n - 1), 1);
+      return;
+    }
+    steps(n / m, out);
+    out->push_back(m);
+    out->insert(out->end(), (size_t)(n % m), 1);
+  }
+};
+
+// Cheapest exact plan for S_k; fills steps if non-null (k must then be small
+// enough for an additive chain to be listed, which an optimal plan only picks
+// for k <= 5).
+int64_t mixed_plan(int64_t k, std::vector<int>* steps) {
+  if (k <= 1) return 0;
+  MixedBest mb;
+  int64_t cost = (k == 2) ? 1 : k - 2;
+  int choice = 0;
+  for (int m : kMixedRadices) {
+    if (k < m) continue;
+    const int64_t r = k % m;
+    const int64_t c = mb.best(k / m).first + mixed_cost(m) + (r > 0 ? r - 1 : 0);
+    if (c < cost) {
+      cost = c;
+      choice = m;
+    }
+  }
+  if (steps) {
+    steps->clear();
+    if (choice == 0) {
+      steps->insert(steps->end(), (size_t)(k - 1), 1);
+    } else {
+      mb.steps(k / choice, steps);
+      steps->push_back(choice);
+      steps->insert(steps->end(), (size_t)(k % choice), 1);
+    }
+  }
+  return cost;
+}
+
 int plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gemms) {
   if (k < 1) return fail(NS_ERR_ARG, "k must be >= 1 (got %lld)", (long long)k);
+  if (method == NS_MIXED) {
+    std::vector<int> st;
+    const int64_t cost = mixed_plan(k, &st);
+    int32_t t = 0;
+    for (int m : st) t += m > 1;
+    if (cost > INT32_MAX || t > NS_MAX_LEVELS) return fail(NS_ERR_RANGE, "k too large");
+    *k_eff = k;
+    *levels = t;
+    *gemms = (int32_t)cost;
+    return NS_OK;
+  }
   if (method == NS_NAIVE) {
     if (k - 1 > INT32_MAX) return fail(NS_ERR_RANGE, "naive k too large");
     *k_eff = k;
@@ -189,6 +269,7 @@ void buffer_counts(int method, int dtype, int* nw, int* n64) {
     case NS_QUINARY: *nw = 7; break;                     // S, S', B, B', U, X1, T
     case NS_RADIX9: *nw = 9; break;                      // S, S', B, B', U, X1, P, Q, T
     case NS_HENSEL: *nw = 4; break;                      // A, R, Y, Y'
+    case NS_MIXED: *nw = 10; break;                      // A, S, S', B, B', U, X1, P, Q, T
     case NS_RADIX9_RESID: *nw = 9; break;                // A, R, Y, Y', U, X1, P, Q, T
     case NS_RADIX15: *nw = 12; break;                    // A, R, Y, Y', P1, L2, R2, L3, R3, L4, R4, F
     default: *nw = 0;
@@ -500,7 +581,59 @@ struct Result {
   Buf S;          // what to copy out (FP64 accumulator for mixed forms)
 };
 
-int run_schedule(Ctx& c, int method, int levels, const Buf& Ain_w, const Buf* Ain64,
+// One step of the exact plan for any k (NS_MIXED).  m > 1: radix-m update of
+// (S, B = A^n); m = 1: additive step S <- S + B, B <- A B.  With `fuse` the
+// plan's final additive step S + A^(new n) is folded into the step's last
+// product (its C is the new power).  Bn receives the new power.
+void mixed_step(Ctx& c, int m, bool fuse, const Buf& A, Buf& S, Buf& S2, Buf* S64, Buf& B, Buf& Bn,
+                Buf& U, Buf& X1, Buf& P, Buf& Q, Buf& T, int lv) {
+  if (m == 1) {
+    if (!S64) {
+      c.gemm(c.eng, A, B, {S, B}, {o(Bn, 1.0), o(S2, fuse ? 1.0 : 0.0, 1.0, 1.0)});
+      std::swap(S, S2);
+    } else if (fuse) {
+      c.gemm(c.eng, A, B, {*S64, B}, {o(Bn, 1.0), o(*S64, 1.0, 1.0, 1.0)});
+    } else {
+      c.gemm(c.eng, A, B, {*S64, B}, {o(Bn, 1.0), o(*S64, 0.0, 1.0, 1.0), o(S, 0.0, 1.0, 1.0)});
+    }
+    return;
+  }
+  if (m == 2) {
+    sum_update(c, S, S2, S64, B);                      // S_2n = S_n (I + A^n)
+    // A^2n = A^n A^n (+ the final additive step S_2n + A^2n)
+    if (!fuse) c.gemm(c.eng, B, B, {}, {o(Bn, 1.0)}, lv);
+    else if (S64) c.gemm(c.eng, B, B, {*S64}, {o(Bn, 1.0), o(*S64, 1.0, 1.0)}, lv);
+    else {
+      c.gemm(c.eng, B, B, {S}, {o(Bn, 1.0), o(S2, 1.0, 1.0)}, lv);
+      std::swap(S, S2);
+    }
+    return;
+  }
+  if (m == 3) {
+    // U = A^2n, T = A^n + A^2n = T3 - I; S_3n = S_n T3; A^3n = U A^n
+    c.gemm(c.eng, B, B, {B}, {o(U, 1.0), o(T, 1.0, 1.0)});
+    sum_update(c, S, S2, S64, T);
+    if (!fuse) c.gemm(c.eng, U, B, {}, {o(Bn, 1.0)}, lv);
+    else if (S64) c.gemm(c.eng, U, B, {*S64}, {o(Bn, 1.0), o(*S64, 1.0, 1.0)}, lv);
+    else {
+      c.gemm(c.eng, U, B, {S}, {o(Bn, 1.0), o(S2, 1.0, 1.0)}, lv);
+      std::swap(S, S2);
+    }
+    return;
+  }
+  if (m == 9) kernel_radix9(c, B, U, X1, P, Q, T);
+  else kernel_quinary(c, B, U, X1, T);
+  sum_update(c, S, S2, S64, T);
+  // telescoping: A^mn = B - (T - I) + (T - I) B
+  if (!fuse) c.gemm(c.eng, T, B, {B, T}, {o(Bn, 1.0, 1.0, -1.0)}, lv);
+  else if (S64) c.gemm(c.eng, T, B, {B, T, *S64}, {o(Bn, 1.0, 1.0, -1.0), o(*S64, 1.0, 1.0, -1.0, 1.0)}, lv);
+  else {
+    c.gemm(c.eng, T, B, {B, T, S}, {o(Bn, 1.0, 1.0, -1.0), o(S2, 1.0, 1.0, -1.0, 1.0)}, lv);
+    std::swap(S, S2);
+  }
+}
+
+int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, const Buf* Ain64,
                  Result* res) {
   const int W64 = (c.eng == ENG_F64) ? 1 : 0;
   Buf A = Ain_w;
@@ -556,6 +689,32 @@ int run_schedule(Ctx& c, int method, int levels, const Buf& Ain_w, const Buf* Ai
       res->S = c.mixed ? S64 : S;
       break;
     }
+    case NS_MIXED: {
+      std::vector<int> steps;
+      mixed_plan(k, &steps);
+      Buf S = c.take(W64), S2 = c.take(W64);
+      Buf Bb[2] = {c.take(W64), c.take(W64)};
+      Buf U = c.take(W64), X1 = c.take(W64), P = c.take(W64), Q = c.take(W64), T = c.take(W64);
+      Buf S64;
+      if (c.mixed) {
+        S64 = c.take(1);
+        c.identity(S64);
+      }
+      c.identity(S);
+      Buf B = A;                  // A^n; the copy of A stays intact for the additive steps
+      int bi = 0, lv = 0;
+      for (size_t i = 0; i < steps.size() && c.status == NS_OK; ++i) {
+        const bool fuse = i + 2 == steps.size() && steps[i + 1] == 1;
+        mixed_step(c, steps[i], fuse, A, S, S2, c.mixed ? &S64 : nullptr, B, Bb[bi], U, X1, P, Q, T,
+                   steps[i] > 1 ? lv : -1);
+        if (steps[i] > 1) ++lv;
+        B = Bb[bi];
+        bi ^= 1;
+        if (fuse) ++i;
+      }
+      res->S = c.mixed ? S64 : S;
+      break;
+    }
     case NS_HENSEL:
     case NS_RADIX9_RESID:
     case NS_RADIX15: {
@@ -605,7 +764,7 @@ int check_args(const void* A, int64_t n, int64_t lda, int64_t k, int method, int
   if (n > 65536) return fail(NS_ERR_RANGE, "n = %lld above the supported 65536", (long long)n);
   if (lda < n || ldo < n) return fail(NS_ERR_ARG, "leading dimension below n");
   if (k < 1) return fail(NS_ERR_ARG, "k must be >= 1 (got %lld)", (long long)k);
-  if (method < NS_NAIVE || method > NS_HENSEL) return fail(NS_ERR_ARG, "unknown method %d", method);
+  if (method < NS_NAIVE || method > NS_MIXED) return fail(NS_ERR_ARG, "unknown method %d", method);
   if (dtype < NS_F64 || dtype > NS_F32_ACC64) return fail(NS_ERR_ARG, "unknown dtype %d", dtype);
   if (method == NS_NAIVE && is_mixed(dtype))
     return fail(NS_ERR_UNSUPPORTED, "the naive Horner form has no FP64-accumulated variant");
@@ -674,7 +833,7 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   }
   if (c.eng == ENG_F16S) c.amax(Aw);
   Result res;
-  if ((st = run_schedule(c, method, levels, Aw, c.mixed ? &A64 : nullptr, &res))) return st;
+  if ((st = run_schedule(c, method, k, levels, Aw, c.mixed ? &A64 : nullptr, &res))) return st;
   if ((st = c.execute())) return st;
   const int out64 = in64;
   NS_HIP(launch_unpad_copy(res.S.p, res.S.f64, c.np, out, out64, n, ldo, s));
@@ -757,7 +916,7 @@ int ns_plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gem
 
 int ns_workspace_bytes(int64_t n, int method, int dtype, size_t* bytes) {
   if (!bytes) return fail(NS_ERR_ARG, "null output pointer");
-  if (n <= 0 || method < NS_NAIVE || method > NS_HENSEL || dtype < NS_F64 || dtype > NS_F32_ACC64)
+  if (n <= 0 || method < NS_NAIVE || method > NS_MIXED || dtype < NS_F64 || dtype > NS_F32_ACC64)
     return fail(NS_ERR_ARG, "bad arguments");
   *bytes = ns::workspace_bytes(n, method, dtype);
   return NS_OK;

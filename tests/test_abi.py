@@ -56,7 +56,7 @@ def test_binding_names_match_abi(ns):
 
 METHOD_MAP = {"naive": "naive", "binary": "binary", "radix9": "radix9", "radix15": "radix15",
               "radix9_resid": "radix9_resid", "quinary": "quinary", "ternary": "ternary",
-              "hensel": "hensel"}
+              "hensel": "hensel", "mixed": "mixed"}
 
 
 @pytest.mark.parametrize("method", list(METHOD_MAP))
@@ -108,3 +108,12 @@ def test_status_strings(ns):
     assert ns.ns_status_string(0) == "ok"
     assert "argument" in ns.ns_status_string(-1)
     assert ns.ns_status_string(-4).startswith("HIP")
+
+
+def test_mixed_plan_matches_oracle_for_every_k(ns):
+    """The library's exact any-k planner (C++) and the oracle's (Python) are
+    written separately; both must find the same product count and number of
+    radix updates for every k up to 2000 and for large k."""
+    ks = list(range(1, 2001)) + [3375, 4095, 4097, 10 ** 6, 10 ** 9 + 7, 2 ** 40 + 5, 2 ** 62 + 1]
+    for k in ks:
+        assert ns.ns_plan(k, "mixed") == series.plan(k, "mixed"), k

@@ -196,3 +196,41 @@ def test_large_symmetric_sampled_columns(ns, method, dtype):
     err = series.rel_fro(got[:, cols], ref)
     say(f"   sampled rel err {err:.3e}")
     assert err < TOL[dtype]
+
+
+# --- exact S_k for any k (no round-up) ---------------------------------------
+
+MIXED_KS = [1, 2, 3, 4, 5, 7, 10, 16, 27, 100, 128, 1000, 3375, 4097]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [37, 300])
+def test_mixed_any_k_parity(ns, dtype, n):
+    """Every plan shape: additive chains (k <= 5), fused final additive steps
+    after each radix (k = 10, 16, 1000, 4097), radix 2, 3, 5 and 9 updates.
+    Nonsymmetric input, so an operand-order mistake in the additive step
+    (B A instead of A B is harmless, but S B instead of B S is not) fails."""
+    g = workloads.gaussian(n, 0.6, 400 + n)
+    for k in MIXED_KS:
+        got, rep = run(ns, g.A, k, "mixed", dtype)
+        ref, orep = series.mixed(oracle_input(g.A, dtype), k)
+        err = series.rel_fro(got, ref)
+        say(f"   k={k} rel err {err:.3e} products {rep['gemms_performed']}")
+        assert err < TOL[dtype], (k, err)
+        assert rep["k_eff"] == k
+        assert rep["gemms_performed"] == rep["gemms_formula"] == orep["products"]
+        assert rep["levels"] == orep["levels"]
+        ln, on = np.array(rep["level_norm"][:rep["levels"]]), np.array(orep["level_norms"])
+        if dtype == "f32":
+            assert np.allclose(ln, on, rtol=1e-3, atol=n * 2.0 ** -22)
+        else:
+            assert np.allclose(ln, on, rtol=1e-9, atol=1e-12)
+
+
+def test_mixed_matches_closed_form_at_k_not_a_power(ns):
+    w = workloads.symmetric(256, 0.95, 21)
+    for k in (1000, 3375, 5000):
+        got, rep = run(ns, w.A, k, "mixed", "f64")
+        closed = series.spectral_form(w.Q, w.lam, k)
+        assert rep["k_eff"] == k
+        assert series.rel_fro(got, closed) < 1e-12, k

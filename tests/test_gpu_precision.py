@@ -97,3 +97,18 @@ def test_mixed_precision_nonsymmetric(ns, method, dtype, n):
     say(f"   rel err {err:.3e}")
     assert err < TOL[dtype]
     assert rep["gemms_performed"] == orep["products"]
+
+
+@pytest.mark.parametrize("dtype", ["f32_acc64", "split_bf16", "f16_scaled"])
+@pytest.mark.parametrize("n", [300, 2048])
+def test_mixed_any_k_precision_forms(ns, dtype, n):
+    """Exact any-k plans in the precision forms: the FP64 running sum takes
+    the additive steps too (S64 += A^n), including the fused last one."""
+    g = workloads.gaussian(n, 0.5, 500 + n)
+    for k in (2, 4, 10, 100, 1000):
+        got, rep = run(ns, g.A, k, "mixed", dtype)
+        ref, orep = series.mixed(g.A, k)
+        err = series.rel_fro(got, ref)
+        say(f"   k={k} rel err {err:.3e}")
+        assert err < TOL[dtype], (k, err)
+        assert rep["gemms_performed"] == orep["products"] and rep["k_eff"] == k
