@@ -274,12 +274,25 @@ struct PolF64 {
   // contiguous KS-double read, and the A reads of a wave cover 4 full rows.
   static constexpr int APITCH = BK;
   // B reads touch 16 rows KS apart; a pitch of BN + 2 doubles puts rows
-  // 2 apart 32 bytes apart in the banks (at most 2-way conflicts).
+  // 2 apart 32 bytes apart in the banks.
+  static constexpr bool SWZ = KS == 2;
   static constexpr int BPITCH = BN + 2;
   // stage the whole tile at once: with one pass per wave-row, a later
   // wave-row would hold its accumulators through the earlier pass's epilogue
   static constexpr int EPI_PASSES = 1;
   static constexpr int DMA_STAGES = 2;    // LDS buffers of the direct-to-LDS k-loop
+  // LDS swizzle of the large tile: 16-byte chunk c of tile row r is stored at
+  // chunk c ^ swz(r); the loaders apply it when they pick each lane's global
+  // chunk.  X rows (256-byte pitch): the four rows of an A read (r & 3 = q)
+  // would otherwise share banks (a 4-way conflict); with the swizzle the A
+  // reads are conflict-free.  Y rows: rows 16 apart move 64 bytes apart.
+  // (Measured on the part: the X swizzle takes the n = 4096 product from 2.78
+  // to 2.54 ms; Y layouts free of every bank conflict, with an unpadded or a
+  // BN + 4 pitch and a three-bit row swizzle, were slower, 2.76 ms.)
+  static __device__ __forceinline__ int a_swz(int r) { return SWZ ? (r & 3) : 0; }
+  static __device__ __forceinline__ int b_swz(int r) {
+    return SWZ ? 4 * ((r >> 4) & 1) : 0;
+  }
   struct Acc {
     double v[NI][NJ];
   };
@@ -295,7 +308,8 @@ struct PolF64 {
     double af[NI][KS];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      const double* src = &As[(wm * WTM + 4 * i + q) * APITCH + KS * kk];
+      const int row = wm * WTM + 4 * i + q, col = KS * kk;
+      const double* src = &As[row * APITCH + ((((col >> 1) ^ a_swz(row)) << 1) | (col & 1))];
       if constexpr (KS % 2 == 0) {
 #pragma unroll
         for (int s = 0; s < KS; s += 2) {
@@ -314,7 +328,8 @@ struct PolF64 {
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const double bf = Bs[(KS * kk + s) * BPITCH + wn * WTN + 4 * j + q];
+        const int row = KS * kk + s, col = wn * WTN + 4 * j + q;
+        const double bf = Bs[row * BPITCH + ((((col >> 1) ^ b_swz(row)) << 1) | (col & 1))];
 #pragma unroll
         for (int i = 0; i < NI; ++i)
           acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf, acc.v[i][j], 0, 0, 0);
@@ -363,6 +378,8 @@ struct PolF32 {
   static constexpr int BPITCH = BN + 4;   // the 4 k-rows of a B read land in distinct banks
   static constexpr int EPI_PASSES = NWM;  // stage one wave-row at a time (bounds the LDS)
   static constexpr int DMA_STAGES = 2;    // LDS buffers of the direct-to-LDS k-loop
+  static __device__ __forceinline__ int a_swz(int) { return 0; }   // no LDS swizzle
+  static __device__ __forceinline__ int b_swz(int) { return 0; }
   struct Acc {
     f4 v[NI][NJ];
   };
@@ -466,13 +483,13 @@ __device__ __forceinline__ void tile_mainloop(const typename P::T* __restrict__ 
   for (int it = 0; it < NA; ++it) {
     const int v = tid + it * P::THREADS, r = v / A_VPR, c = v % A_VPR;
     ga[it] = (size_t)(row0 + r) * ld + c * EPV;
-    sa[it] = r * P::APITCH + c * EPV;
+    sa[it] = r * P::APITCH + (c ^ P::a_swz(r)) * EPV;     // the policy's LDS swizzle
   }
 #pragma unroll
   for (int it = 0; it < NB; ++it) {
     const int v = tid + it * P::THREADS, r = v / B_VPR, c = v % B_VPR;
     gb[it] = (size_t)r * ld + col0 + c * EPV;
-    sb[it] = r * P::BPITCH + c * EPV;
+    sb[it] = r * P::BPITCH + (c ^ P::b_swz(r)) * EPV;
   }
   uint4 ra[NA], rb[NB];
   const int nk = K / P::BK;
@@ -527,14 +544,15 @@ struct DmaPlan {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int ins = wave + i * D::NW;                // this instruction's 1 KB run of the X tile
-      const int v = ins * 64 + lane, r = v / ROW_VEC, c = (v % ROW_VEC) * EPV;
+      // LDS chunk v % ROW_VEC of row r holds global chunk (v % ROW_VEC) ^ a_swz(r)
+      const int v = ins * 64 + lane, r = v / ROW_VEC, c = ((v % ROW_VEC) ^ P::a_swz(r)) * EPV;
       a_off[i] = (uint32_t)((row0 + r) * ld + c);
       a_lds[i] = ins * (1024 / (int)sizeof(T));
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int r = wave + i * D::NW;                  // one Y-tile row per instruction
-      b_off[i] = (uint32_t)(r * ld + col0 + lane * EPV);
+      b_off[i] = (uint32_t)(r * ld + col0 + (lane ^ P::b_swz(r)) * EPV);
       b_lds[i] = r * P::BPITCH;
     }
   }
