@@ -15,6 +15,12 @@ oracle evaluates is the POLISHED table: the printed point moved by a
 minimum-norm Gauss-Newton iteration onto the set of exact prefix solutions
 (``polish15.py`` writes it; each entry stays within rounding distance of its
 printed value).  The polished table is read from ``radix15_polished.txt``.
+
+A second, contraction-aware table (``contract15.py`` writes it) is another
+point of the same prefix-exact set, chosen so that the error map
+E(z) = z^15 p(z) has a p with nonnegative coefficients: |E(z)| <= |z|^15 on
+the unit disk.  ``contract_start()`` is its six-decimal start point and
+``contract_polished()`` the polished doubles.
 """
 
 import os
@@ -41,6 +47,32 @@ NAMES: List[str] = (
 )
 
 POLISHED_PATH = os.path.join(os.path.dirname(__file__), "radix15_polished.txt")
+
+
+CONTRACT_START_PATH = os.path.join(os.path.dirname(__file__), "radix15c_start.txt")
+CONTRACT_POLISHED_PATH = os.path.join(os.path.dirname(__file__), "radix15c_polished.txt")
+
+
+def contract_start() -> List[float]:
+    """Six-decimal start point of the contraction-aware table."""
+    return _read(CONTRACT_START_PATH, float)
+
+
+def contract_polished() -> List[float]:
+    """The contraction-aware table as doubles."""
+    return _read(CONTRACT_POLISHED_PATH, float.fromhex)
+
+
+def _read(path, conv) -> List[float]:
+    vals = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                vals.append(conv(line.split()[1]))
+    if len(vals) != 28:
+        raise ValueError(f"{path}: expected 28 coefficients, got {len(vals)}")
+    return vals
 
 
 def polished() -> List[float]:

@@ -82,10 +82,10 @@ def _levels(k: int, m: int) -> int:
 # product counts (Sec. 2.1-2.2 cost model; Sec. 5.4 eq. (9); Table 2)
 # ---------------------------------------------------------------------------
 
-RADIX = {"binary": 2, "ternary": 3, "quinary": 5, "radix9": 9, "radix15": 15,
+RADIX = {"binary": 2, "ternary": 3, "quinary": 5, "radix9": 9, "radix15": 15, "radix15c": 15,
          "radix9_resid": 9, "quinary_resid": 5, "hensel": 2}
 # products per update: mu_m + 2 (kernel + concatenation + power/residual)
-PER_LEVEL = {"binary": 2, "ternary": 3, "quinary": 4, "radix9": 5, "radix15": 6,
+PER_LEVEL = {"binary": 2, "ternary": 3, "quinary": 4, "radix9": 5, "radix15": 6, "radix15c": 6,
              "radix9_resid": 5, "quinary_resid": 4, "hensel": 2}
 
 
@@ -347,6 +347,14 @@ def radix15(A: np.ndarray, k: int, c28: Optional[Sequence[float]] = None):
     return general_radix(A, k, "radix15", lambda B, mm: kernel_radix15(B, mm, c28))
 
 
+def radix15c(A: np.ndarray, k: int):
+    """Radix-15 in the general framework with the contraction-aware table
+    (same circuit and schedule as radix15; E(z) = z^15 p(z) with p's
+    coefficients nonnegative, so |E(z)| <= |z|^15 on the unit disk)."""
+    c28 = coeffs15.contract_polished()
+    return general_radix(A, k, "radix15c", lambda B, mm: kernel_radix15(B, mm, c28))
+
+
 def radix9_resid(A: np.ndarray, k: int):
     """The exact radix-9 kernel run through the general framework (Sec. 5.5,
     exact radix-m special case: then R_n = A^(9^n))."""
@@ -409,6 +417,7 @@ SCHEDULES: Dict[str, Callable] = {
     "quinary": quinary,
     "radix9": radix9,
     "radix15": radix15,
+    "radix15c": radix15c,
     "radix9_resid": radix9_resid,
     "quinary_resid": quinary_resid,
     "hensel": hensel,

@@ -7,6 +7,7 @@ identities that hold for any polynomial, or exact rational surrogates.
 
 from fractions import Fraction
 
+import numpy as np
 import pytest
 
 from conftest import golden_rows
@@ -133,6 +134,64 @@ def test_radix15_is_approximate_kernel():
     assert abs(poly.coeff(g, 0) - 1) < 1e-15
     assert all(abs(poly.coeff(g, j)) < 1e-15 for j in range(1, 15))
     assert abs(poly.coeff(g, 15)) > 0.1
+
+
+# --- contraction-aware radix-15 table ------------------------------------------
+
+def _error_quadratic(c28):
+    """(c0, c1, c2) with E(z) = z^15 (c0 + c1 z + c2 z^2) + (prefix rounding), from
+    the exact rational composition of the circuit."""
+    f = poly.radix15_poly(c28)
+    E = poly.error_map(f)
+    assert len(E) - 1 == 17
+    return f, [poly.coeff(E, 15), poly.coeff(E, 16), poly.coeff(E, 17)]
+
+
+def test_contract_table_is_prefix_exact_with_nonnegative_error_quadratic():
+    """Prefix conditions of Sec. 4.2 to the rounding of the doubles, and
+    E(z) = z^15 p(z) with p's coefficients all >= 0.11: |p(z)| <= 1 on the unit
+    disk (they sum to 1 exactly up to the prefix rounding)."""
+    f, (c0, c1, c2) = _error_quadratic(coeffs15.contract_polished())
+    assert float(poly.prefix_error(f, 15)) < 1e-15
+    E = poly.error_map(f)
+    assert all(abs(poly.coeff(E, j)) < 1e-14 for j in range(15))
+    assert min(c0, c1, c2) > Fraction(11, 100)
+    assert abs(c0 + c1 + c2 - 1) < 1e-14
+    # p's coefficients are 1 - a15, a15 - a16, a16 (Definition 5.2 expanded,
+    # exactly so up to the prefix rounding of [f]_14)
+    a15, a16 = poly.coeff(f, 15), poly.coeff(f, 16)
+    assert abs(c0 - (1 - a15)) < 1e-14 and c1 == a15 - a16 and c2 == a16
+
+
+def test_contract_table_contracts_where_the_app_b_table_does_not():
+    """|E(z)| <= |z|^15 on the unit circle for the new table; the App. B table
+    has |E(-0.99)| = 1.32 > 0.99 (the divergence of the rho = 0.99 workload)."""
+    _, q = _error_quadratic(coeffs15.contract_polished())
+    _, q_b = _error_quadratic(coeffs15.polished())
+    th = np.linspace(0, 2 * np.pi, 721)
+    z = np.exp(1j * th)
+    p = sum(float(c) * z ** i for i, c in enumerate(q))
+    assert np.abs(p).max() <= 1 + 1e-12
+    r = -0.99
+    e_b = abs(r ** 15 * sum(float(c) * r ** i for i, c in enumerate(q_b)))
+    e_c = abs(r ** 15 * sum(float(c) * r ** i for i, c in enumerate(q)))
+    assert e_b > 1.3 and e_c < 0.99 ** 15
+
+
+def test_contract_table_regenerates_from_its_start_point():
+    """Polishing the stored six-decimal start point reproduces the table, and
+    every coefficient is within half a unit of the sixth decimal of it."""
+    from oracle import contract15
+    assert open(contract15.POLISHED_PATH).read() == contract15.render_polished(coeffs15.contract_start())
+    for name, x, s in zip(coeffs15.NAMES, coeffs15.contract_polished(), coeffs15.contract_start()):
+        assert abs(x - s) <= 5e-7 + 1e-12, name
+
+
+@pytest.mark.parametrize("idx", [0, 9, 17, 27])
+def test_contract_table_planted_mistake_is_caught(idx):
+    c = list(coeffs15.contract_polished())
+    c[idx] += 1e-3
+    assert float(poly.prefix_error(poly.radix15_poly(c), 15)) > 1e-7
 
 
 # --- framework lemmas on exact surrogates (Sec. 5.1-5.2) ----------------------

@@ -326,3 +326,17 @@ def test_mixed_closed_form_large_k():
         ref = series.closed_form(w.A, k)
         assert series.rel_fro(S, ref) < 1e-12, k
         assert rep["products"] == series.mixed_plan(k)[0]
+
+
+def test_radix15c_converges_where_radix15_diverges():
+    """Nonsymmetric N(0,1)/sqrt(n) scaled to rho_hat = 0.99: the App. B kernel's
+    residual iteration grows (|E(-0.99)| > 0.99), the contraction-aware kernel
+    reaches the closed form (I - A)^{-1} (I - A^k) at k = 15^3."""
+    g = workloads.gaussian(96, 0.99, 17)
+    ref = series.closed_form(g.A, 3375)
+    S_c, rep_c = series.radix15c(g.A, 3375)
+    S_b, rep_b = series.radix15(g.A, 3375)
+    assert series.rel_fro(S_c, ref) < 1e-12
+    assert rep_c["level_norms"][-1] < 1e-10
+    assert rep_b["level_norms"][-1] > rep_b["level_norms"][0] > 1.0
+    assert rep_c["products"] == rep_b["products"] == 18
