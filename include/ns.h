@@ -75,7 +75,14 @@ enum ns_method {
      product's epilogue at no cost.  Ties between plans of equal cost go, in
      order, to the additive chain from 1, then m = 9, 5, 3, 2 as the last
      radix update.  levels counts the radix updates. */
-  NS_MIXED = 8
+  NS_MIXED = 8,
+  /* NS_RADIX15 with a contraction-aware coefficient table: another point of
+     the prefix-exact set of Sec. 4.2, whose error map E(z) = z^15 (c0 + c1 z
+     + c2 z^2) (Definition 5.2) has c0, c1, c2 > 0 and hence |E(z)| <= |z|^15
+     on the unit disk, so the iteration of eq. (8) converges for every A with
+     spectral radius below 1 (the App. B table has c1 < 0 and diverges near
+     eigenvalue -0.99).  See ns_radix15c_coeffs.  6 ceil(log15 k) products. */
+  NS_RADIX15C = 9
 };
 
 /* ---- compute precision ------------------------------------------------ */
@@ -199,6 +206,11 @@ int ns_autotune_batched(ns_handle* h, const void* A_packed, const int64_t* off_d
    (Sec. 4.1 eq. (4)-(5)); derived at load time from the App. B digits by the
    library's own minimum-norm Gauss-Newton.  Outputs may be null except c28. */
 int ns_radix15_coeffs(double c28[28], double* prefix_err, double* spill15, double* spill16);
+
+/* The contraction-aware table of NS_RADIX15C, same order and outputs: its
+   six-decimal start point (a minimum-norm point of the prefix-exact set with
+   c0, c1, c2 >= 0.12) polished by the same Gauss-Newton. */
+int ns_radix15c_coeffs(double c28[28], double* prefix_err, double* spill15, double* spill16);
 
 /* Per-product timing for roofline measurement: when enabled, every product
    launch issued by ns_eval_ex on this handle is bracketed by HIP events on the

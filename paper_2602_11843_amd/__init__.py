@@ -16,10 +16,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libns.so")
 
 # methods (enum ns_method)
-NAIVE, BINARY, RADIX9, RADIX15, RADIX9_RESID, QUINARY, TERNARY, HENSEL, MIXED = range(9)
+NAIVE, BINARY, RADIX9, RADIX15, RADIX9_RESID, QUINARY, TERNARY, HENSEL, MIXED, RADIX15C = range(10)
 METHODS = {"naive": NAIVE, "binary": BINARY, "radix9": RADIX9, "radix15": RADIX15,
            "radix9_resid": RADIX9_RESID, "quinary": QUINARY, "ternary": TERNARY,
-           "hensel": HENSEL, "mixed": MIXED}
+           "hensel": HENSEL, "mixed": MIXED, "radix15c": RADIX15C}
 # compute precision (enum ns_dtype)
 F64, F32, SPLIT_BF16, F16_SCALED, F32_ACC64 = range(5)
 DTYPES = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16, "f16_scaled": F16_SCALED,
@@ -82,6 +82,8 @@ _SIGNATURES = {
                                            ctypes.POINTER(_I32)]),
     "ns_radix15_coeffs": (ctypes.c_int, [ctypes.POINTER(_D), ctypes.POINTER(_D),
                                          ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "ns_radix15c_coeffs": (ctypes.c_int, [ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                          ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "ns_set_product_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "ns_product_timing": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_D),
                                          ctypes.POINTER(_D), ctypes.c_int]),
@@ -137,6 +139,15 @@ def ns_radix15_coeffs():
     pe, s15, s16 = _D(), _D(), _D()
     _check(lib.ns_radix15_coeffs(c, ctypes.byref(pe), ctypes.byref(s15), ctypes.byref(s16)),
            "ns_radix15_coeffs")
+    return list(c), pe.value, s15.value, s16.value
+
+
+def ns_radix15c_coeffs():
+    """(28 coefficients, prefix error, a15, a16) of the contraction-aware table."""
+    c = (_D * 28)()
+    pe, s15, s16 = _D(), _D(), _D()
+    _check(lib.ns_radix15c_coeffs(c, ctypes.byref(pe), ctypes.byref(s15), ctypes.byref(s16)),
+           "ns_radix15c_coeffs")
     return list(c), pe.value, s15.value, s16.value
 
 

@@ -31,6 +31,7 @@
 
 namespace ns {
 bool radix15_table(double c[28], double* prefix_err, double* s15, double* s16);
+bool radix15c_table(double c[28], double* prefix_err, double* s15, double* s16);
 int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, const int32_t* n_dev,
                  const int32_t* n_host, int32_t batch, int64_t k, int method, int dtype,
                  void* out_packed, hipStream_t stream, ns_report* rep);
@@ -108,7 +109,8 @@ bool is_mixed(int dtype) {
   return dtype == NS_SPLIT_BF16 || dtype == NS_F16_SCALED || dtype == NS_F32_ACC64;
 }
 bool is_residual(int method) {
-  return method == NS_RADIX15 || method == NS_RADIX9_RESID || method == NS_HENSEL;
+  return method == NS_RADIX15 || method == NS_RADIX15C || method == NS_RADIX9_RESID ||
+         method == NS_HENSEL;
 }
 Engine work_engine(int dtype) {
   switch (dtype) {
@@ -126,7 +128,7 @@ int radix_of(int method) {
     case NS_TERNARY: return 3;
     case NS_QUINARY: return 5;
     case NS_RADIX9: case NS_RADIX9_RESID: return 9;
-    case NS_RADIX15: return 15;
+    case NS_RADIX15: case NS_RADIX15C: return 15;
     case NS_HENSEL: return 2;
     default: return 0;
   }
@@ -138,7 +140,7 @@ int per_level(int method) {
     case NS_TERNARY: return 3;
     case NS_QUINARY: return 4;
     case NS_RADIX9: case NS_RADIX9_RESID: return 5;
-    case NS_RADIX15: return 6;
+    case NS_RADIX15: case NS_RADIX15C: return 6;
     case NS_HENSEL: return 2;
     default: return 0;
   }
@@ -271,7 +273,8 @@ void buffer_counts(int method, int dtype, int* nw, int* n64) {
     case NS_HENSEL: *nw = 4; break;                      // A, R, Y, Y'
     case NS_MIXED: *nw = 10; break;                      // A, S, S', B, B', U, X1, P, Q, T
     case NS_RADIX9_RESID: *nw = 9; break;                // A, R, Y, Y', U, X1, P, Q, T
-    case NS_RADIX15: *nw = 12; break;                    // A, R, Y, Y', P1, L2, R2, L3, R3, L4, R4, F
+    case NS_RADIX15:
+    case NS_RADIX15C: *nw = 12; break;                   // A, R, Y, Y', P1, L2, R2, L3, R3, L4, R4, F
     default: *nw = 0;
   }
   *n64 = mixed ? (is_residual(method) ? 2 : 1) : 0;    // Y64 + A64, or S64
@@ -717,7 +720,8 @@ int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, co
     }
     case NS_HENSEL:
     case NS_RADIX9_RESID:
-    case NS_RADIX15: {
+    case NS_RADIX15:
+    case NS_RADIX15C: {
       // Y_0 = I, R_0 = A;  Y <- Y f(R);  R <- I - (I - A) Y   (eq. (8))
       Buf Y = c.take(W64), Y2 = c.take(W64), R = c.take(W64);
       Buf Y64, A64;
@@ -732,8 +736,9 @@ int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, co
       double k15[28];
       Buf U, X1, P, Q, T, P1, L2, R2, L3, R3, L4, R4, F;
       if (method == NS_RADIX9_RESID) { U = c.take(W64); X1 = c.take(W64); P = c.take(W64); Q = c.take(W64); T = c.take(W64); }
-      if (method == NS_RADIX15) {
-        radix15_table(k15, nullptr, nullptr, nullptr);
+      if (method == NS_RADIX15 || method == NS_RADIX15C) {
+        if (method == NS_RADIX15) radix15_table(k15, nullptr, nullptr, nullptr);
+        else radix15c_table(k15, nullptr, nullptr, nullptr);
         P1 = c.take(W64); L2 = c.take(W64); R2 = c.take(W64); L3 = c.take(W64);
         R3 = c.take(W64); L4 = c.take(W64); R4 = c.take(W64); F = c.take(W64);
       }
@@ -764,7 +769,7 @@ int check_args(const void* A, int64_t n, int64_t lda, int64_t k, int method, int
   if (n > 65536) return fail(NS_ERR_RANGE, "n = %lld above the supported 65536", (long long)n);
   if (lda < n || ldo < n) return fail(NS_ERR_ARG, "leading dimension below n");
   if (k < 1) return fail(NS_ERR_ARG, "k must be >= 1 (got %lld)", (long long)k);
-  if (method < NS_NAIVE || method > NS_MIXED) return fail(NS_ERR_ARG, "unknown method %d", method);
+  if (method < NS_NAIVE || method > NS_RADIX15C) return fail(NS_ERR_ARG, "unknown method %d", method);
   if (dtype < NS_F64 || dtype > NS_F32_ACC64) return fail(NS_ERR_ARG, "unknown dtype %d", dtype);
   if (method == NS_NAIVE && is_mixed(dtype))
     return fail(NS_ERR_UNSUPPORTED, "the naive Horner form has no FP64-accumulated variant");
@@ -854,9 +859,10 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
     rep->dtype = dtype;
     if (method != NS_NAIVE)
       for (int i = 0; i < levels && i < NS_MAX_LEVELS; ++i) rep->level_norm[i] = std::sqrt(hs.level_sumsq[i]);
-    if (method == NS_RADIX15) {
+    if (method == NS_RADIX15 || method == NS_RADIX15C) {
       double cc[28];
-      radix15_table(cc, &rep->kernel_prefix_err, &rep->spill15, &rep->spill16);
+      if (method == NS_RADIX15) radix15_table(cc, &rep->kernel_prefix_err, &rep->spill15, &rep->spill16);
+      else radix15c_table(cc, &rep->kernel_prefix_err, &rep->spill15, &rep->spill16);
     }
   }
   return NS_OK;
@@ -916,7 +922,7 @@ int ns_plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gem
 
 int ns_workspace_bytes(int64_t n, int method, int dtype, size_t* bytes) {
   if (!bytes) return fail(NS_ERR_ARG, "null output pointer");
-  if (n <= 0 || method < NS_NAIVE || method > NS_MIXED || dtype < NS_F64 || dtype > NS_F32_ACC64)
+  if (n <= 0 || method < NS_NAIVE || method > NS_RADIX15C || dtype < NS_F64 || dtype > NS_F32_ACC64)
     return fail(NS_ERR_ARG, "bad arguments");
   *bytes = ns::workspace_bytes(n, method, dtype);
   return NS_OK;
@@ -990,6 +996,13 @@ int ns_autotune_batched(ns_handle* h, const void* A_packed, const int64_t* off_d
 int ns_radix15_coeffs(double c28[28], double* prefix_err, double* spill15, double* spill16) {
   if (!c28) return fail(NS_ERR_ARG, "null output");
   if (!ns::radix15_table(c28, prefix_err, spill15, spill16))
+    return fail(NS_ERR_RANGE, "radix-15 coefficient polish did not converge");
+  return NS_OK;
+}
+
+int ns_radix15c_coeffs(double c28[28], double* prefix_err, double* spill15, double* spill16) {
+  if (!c28) return fail(NS_ERR_ARG, "null output");
+  if (!ns::radix15c_table(c28, prefix_err, spill15, spill16))
     return fail(NS_ERR_RANGE, "radix-15 coefficient polish did not converge");
   return NS_OK;
 }

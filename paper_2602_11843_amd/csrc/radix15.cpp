@@ -9,6 +9,14 @@
 // iteration (x <- x - J^T (J J^T)^{-1} r, r_j = [T15~]_j - 1, j = 0..14) in
 // extended precision, with the Jacobian from forward-mode differentiation of
 // the circuit, and rounds the limit to double.  This runs once per process.
+//
+// A second table is another point of the same prefix-exact set, chosen for
+// contraction: for any prefix-exact kernel E(z) = 1 - (1 - z) f(z) equals
+// z^15 (c0 + c1 z + c2 z^2) with c0 + c1 + c2 = 1, and this point has all three
+// positive (0.387, 0.469, 0.145), so |E(z)| <= |z|^15 on the unit disk; the
+// App. B point has c1 < 0 and |E(-0.99)| = 1.32.  Its six-decimal start values
+// come from a minimum-norm search over the prefix-exact circuits with those
+// signs; the library polishes them exactly as it polishes App. B.
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -26,6 +34,14 @@ const double kPrinted[NP] = {
     0.263, 0.919, 0.842, 0.819,  0.184, 0.068, 0.134, -1.405,
     -0.005, -1.385, 0.022, 0.122, 0.275,  -0.701, 0.602, -0.624, -0.137, 0.328,
     0.078, 1.778, 0.664, -0.024};
+
+// contraction-aware start point, same order
+const double kContractStart[NP] = {
+    -0.080640, 0.767151, 1.013267,  0.244248, 0.361818, 1.196313,
+    0.152070, -0.005236, 0.232342, 0.859142,  -0.273960, -0.360528, 0.558567, -0.546103,
+    0.031022, -0.162034, -0.679246, 0.361310, 0.470000,
+    -0.404032, -0.017359, 0.403484, -0.306344, 0.647957,
+    0.803348, 0.395265, 0.600823, -0.417747};
 
 struct Poly {
   R c[DEG];
@@ -122,10 +138,10 @@ struct Table {
   bool ok;
 };
 
-Table build() {
+Table build(const double* start) {
   Table t{};
   R x[NP];
-  for (int p = 0; p < NP; ++p) x[p] = kPrinted[p];
+  for (int p = 0; p < NP; ++p) x[p] = start[p];
   static DPoly T;
   for (int it = 0; it < 30; ++it) {
     circuit(x, T);
@@ -166,12 +182,24 @@ Table build() {
 
 }  // namespace
 
-// Returns the polished table (computed on first use).  ok = false if the
-// iteration failed, which would be a defect in this file.
+// Returns the polished App. B table (computed on first use).  ok = false if
+// the iteration failed, which would be a defect in this file.
 bool radix15_table(double c[28], double* prefix_err, double* s15, double* s16) {
   static std::once_flag once;
   static Table tab;
-  std::call_once(once, [] { tab = build(); });
+  std::call_once(once, [] { tab = build(kPrinted); });
+  std::memcpy(c, tab.c, sizeof(tab.c));
+  if (prefix_err) *prefix_err = tab.prefix_err;
+  if (s15) *s15 = tab.spill15;
+  if (s16) *s16 = tab.spill16;
+  return tab.ok;
+}
+
+// The polished contraction-aware table, likewise.
+bool radix15c_table(double c[28], double* prefix_err, double* s15, double* s16) {
+  static std::once_flag once;
+  static Table tab;
+  std::call_once(once, [] { tab = build(kContractStart); });
   std::memcpy(c, tab.c, sizeof(tab.c));
   if (prefix_err) *prefix_err = tab.prefix_err;
   if (s15) *s15 = tab.spill15;

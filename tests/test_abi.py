@@ -56,7 +56,7 @@ def test_binding_names_match_abi(ns):
 
 METHOD_MAP = {"naive": "naive", "binary": "binary", "radix9": "radix9", "radix15": "radix15",
               "radix9_resid": "radix9_resid", "quinary": "quinary", "ternary": "ternary",
-              "hensel": "hensel", "mixed": "mixed"}
+              "hensel": "hensel", "mixed": "mixed", "radix15c": "radix15c"}
 
 
 @pytest.mark.parametrize("method", list(METHOD_MAP))
@@ -94,6 +94,18 @@ def test_radix15_table_agrees_with_oracle(ns):
         assert abs(a - b) <= 4 * abs(b) * 2.0 ** -52
     assert pe < 1e-15
     assert round(s15, 3) == 0.185 and round(s16, 3) == 0.458
+
+
+def test_radix15c_table_agrees_with_oracle(ns):
+    """The contraction-aware table: the library polishes its own copy of the
+    six-decimal start point; it must land on the oracle's polished doubles,
+    with the error quadratic's coefficients 1 - a15, a15 - a16, a16 positive."""
+    c, pe, s15, s16 = ns.ns_radix15c_coeffs()
+    ref = coeffs15.contract_polished()
+    for a, b in zip(c, ref):
+        assert abs(a - b) <= 4 * abs(b) * 2.0 ** -52
+    assert pe < 1e-15
+    assert min(1 - s15, s15 - s16, s16) > 0.11
 
 
 def test_workspace_bytes(ns):

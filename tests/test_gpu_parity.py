@@ -53,14 +53,14 @@ def run(ns, A, k, method, dtype, **kw):
 
 ORACLE_NAME = {"naive": "naive", "binary": "binary", "radix9": "radix9", "radix15": "radix15",
                "radix9_resid": "radix9_resid", "quinary": "quinary", "ternary": "ternary",
-               "hensel": "hensel"}
+               "hensel": "hensel", "radix15c": "radix15c"}
 
 
 # --- small sizes: every method x {f64, f32}, several tiles and ragged tails ---
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("method", ["naive", "binary", "radix9", "radix15", "radix9_resid",
-                                    "quinary", "ternary", "hensel"])
+                                    "quinary", "ternary", "hensel", "radix15c"])
 @pytest.mark.parametrize("n", [37, 256, 300])
 def test_small_parity(ns, method, dtype, n):
     w = workloads.symmetric(n, 0.9, 100 + n)
@@ -85,7 +85,7 @@ def test_small_parity(ns, method, dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("method", ["binary", "radix9", "radix15"])
+@pytest.mark.parametrize("method", ["binary", "radix9", "radix15", "radix15c"])
 def test_nonsymmetric_parity(ns, method, dtype):
     g = workloads.gaussian(512, 0.95, 7)
     k = 225 if method == "radix15" else 81
