@@ -335,7 +335,7 @@ def bench_precision_sym(args, torch, ns):
                       "seed": w.seed, "lam": "U[-0.9,0.9]"})
     line["legs"] = {f"{m}:{d}": {**rnd(r), "rel_err_vs_fp64_definition_sampled": errs[(m, d)]}
                     for (m, d), r in res.items()}
-    line["roofline"] = roofline_from_leg(main, n, "gemm_panel_kernel<PolPanel<2,4,4,2,true>>", "bf16",
+    line["roofline"] = roofline_from_leg(main, n, "gemm_panel_kernel<PolPanel<2,4,4,2,true,1,2,2>>", "bf16",
                                          mfma_per_logical=3.0)
     line["cpu_baseline"] = cpu
     return line

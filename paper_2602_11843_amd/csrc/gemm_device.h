@@ -141,13 +141,13 @@ __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, c
 // The same epilogue when every Z input and every output is FP32: float
 // arithmetic, no per-element type branches (fewer registers; used by the FP32
 // engine whenever a product's inputs and outputs are all FP32, and always by
-// the batched kernel, so both produce identical bits).
-template <int VEC, bool AMAXO = false>
-__device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int col,
-                                            const double (&c)[VEC], EpiStateT<AMAXO>& st) {
-  static_assert(VEC == 4, "float epilogue works on float4 vectors");
-  const size_t idx = (size_t)row * p.ld + col;
-  float z[kMaxZ][VEC];
+// the batched kernel, so both produce identical bits).  Split into the Z loads
+// and the arithmetic + stores, so that a caller can issue the loads of two
+// vectors before the stores of the first (epi_vec_f32_pair): a store to an
+// output may alias a Z input at the same element, which keeps the compiler from
+// moving the next vector's loads above it, and one load at a time leaves the
+// epilogue waiting on memory latency.
+__device__ __forceinline__ void epi_load_f32(const GemmParams& p, size_t idx, float (&z)[kMaxZ][4]) {
 #pragma unroll
   for (int i = 0; i < kMaxZ; ++i) {
     if (i < p.nz) {
@@ -155,9 +155,16 @@ __device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int co
       z[i][0] = t.x; z[i][1] = t.y; z[i][2] = t.z; z[i][3] = t.w;
     } else {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) z[i][e] = 0.f;
+      for (int e = 0; e < 4; ++e) z[i][e] = 0.f;
     }
   }
+}
+
+template <bool AMAXO>
+__device__ __forceinline__ void epi_apply_f32(const GemmParams& p, int row, int col, size_t idx,
+                                              const double (&c)[4], const float (&z)[kMaxZ][4],
+                                              EpiStateT<AMAXO>& st) {
+  constexpr int VEC = 4;
 #pragma unroll
   for (int o = 0; o < kMaxOut; ++o) {
     if (o >= p.no) break;
@@ -187,6 +194,29 @@ __device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int co
       }
     }
   }
+}
+
+template <int VEC, bool AMAXO = false>
+__device__ __forceinline__ void epi_vec_f32(const GemmParams& p, int row, int col,
+                                            const double (&c)[VEC], EpiStateT<AMAXO>& st) {
+  static_assert(VEC == 4, "float epilogue works on float4 vectors");
+  const size_t idx = (size_t)row * p.ld + col;
+  float z[kMaxZ][4];
+  epi_load_f32(p, idx, z);
+  epi_apply_f32<AMAXO>(p, row, col, idx, c, z, st);
+}
+
+// Two vectors: both vectors' Z loads first, then the arithmetic and stores.
+template <bool AMAXO = false>
+__device__ __forceinline__ void epi_vec_f32_pair(const GemmParams& p, int row0, int col0,
+                                                 const double (&c0)[4], int row1, int col1,
+                                                 const double (&c1)[4], EpiStateT<AMAXO>& st) {
+  const size_t i0 = (size_t)row0 * p.ld + col0, i1 = (size_t)row1 * p.ld + col1;
+  float z0[kMaxZ][4], z1[kMaxZ][4];
+  epi_load_f32(p, i0, z0);
+  epi_load_f32(p, i1, z1);
+  epi_apply_f32<AMAXO>(p, row0, col0, i0, c0, z0, st);
+  epi_apply_f32<AMAXO>(p, row1, col1, i1, c1, z1, st);
 }
 
 // true if every Z input and output of the block is FP32
@@ -641,13 +671,33 @@ __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmPa
   for (int pass = 0; pass < P::EPI_PASSES; ++pass) {
     if (wm / WROWS == pass) P::stage(acc, lane, wn, C + (wm % WROWS) * P::WTM * CPITCH, CPITCH);
     __syncthreads();
-    for (int v = tid; v < PROWS * VPR; v += P::THREADS) {
-      const int r = v / VPR, cv = (v % VPR) * VEC;
-      double c[VEC];
+    if constexpr (F32) {
+      // two vectors per step (their Z loads ahead of their stores)
+      for (int v = tid; v < PROWS * VPR; v += 2 * P::THREADS) {
+        const int r = v / VPR, cv = (v % VPR) * VEC;
+        double c[VEC];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
-      if constexpr (F32) epi_vec_f32<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
-      else epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+        for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
+        const int v2 = v + P::THREADS;
+        if (v2 < PROWS * VPR) {
+          const int r2 = v2 / VPR, cv2 = (v2 % VPR) * VEC;
+          double c2[VEC];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) c2[e] = (double)C[r2 * CPITCH + cv2 + e];
+          epi_vec_f32_pair(p, row0 + pass * PROWS + r, col0 + cv, c, row0 + pass * PROWS + r2,
+                           col0 + cv2, c2, st);
+        } else {
+          epi_vec_f32<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+        }
+      }
+    } else {
+      for (int v = tid; v < PROWS * VPR; v += P::THREADS) {
+        const int r = v / VPR, cv = (v % VPR) * VEC;
+        double c[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
+        epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+      }
     }
     __syncthreads();
   }

@@ -103,8 +103,9 @@ __global__ __launch_bounds__(256) void to_panels_kernel(const float* __restrict_
 // loader copies one 1 KB block.
 // ---------------------------------------------------------------------------
 template <int NWM_, int NWN_, int NI_, int NJ_, bool SPLIT_, int KSLAB_, int STAGES_, int EFR_,
-          int MINB_ = 1>
+          int MINB_ = 1, bool EPI2_ = true>
 struct PolPanel {
+  static constexpr bool EPI2 = EPI2_;     // FP32 epilogue: two vectors per step
   static constexpr int MINB = MINB_;                          // workgroups per CU to fit
   static constexpr bool SPLIT = SPLIT_;
   static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_, KSLAB = KSLAB_;
@@ -299,21 +300,42 @@ __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_panel_kernel(const M
     }
     __syncthreads();
     const int grow = row0 + pw * Q::WTM + pi * PROWS;
-    for (int v = tid; v < PROWS * VPR; v += Q::THREADS) {
-      const int r = v / VPR, cv = (v % VPR) * VEC;
-      double c[VEC];
+    if (Q::EPI2 && f32_out) {
+      // two vectors per step (their Z loads ahead of their stores)
+      for (int v = tid; v < PROWS * VPR; v += 2 * Q::THREADS) {
+        const int r = v / VPR, cv = (v % VPR) * VEC;
+        double c[VEC];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e];
-      if (f32_out) epi_vec_f32<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
-      else epi_vec<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
+        for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e];
+        const int v2 = v + Q::THREADS;
+        if (v2 < PROWS * VPR) {
+          const int r2 = v2 / VPR, cv2 = (v2 % VPR) * VEC;
+          double c2[VEC];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) c2[e] = (double)C[r2 * Q::CPITCH + cv2 + e];
+          epi_vec_f32_pair<!Q::SPLIT>(p, grow + r, col0 + cv, c, grow + r2, col0 + cv2, c2, st);
+        } else {
+          epi_vec_f32<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
+        }
+      }
+    } else {
+      for (int v = tid; v < PROWS * VPR; v += Q::THREADS) {
+        const int r = v / VPR, cv = (v % VPR) * VEC;
+        double c[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e];
+        if (f32_out) epi_vec_f32<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
+        else epi_vec<VEC, !Q::SPLIT>(p, grow + r, col0 + cv, c, st);
+      }
     }
     __syncthreads();
   }
   publish_stats<Q::THREADS, !Q::SPLIT>(p, st, reinterpret_cast<double*>(smem));
 }
 
-using BF3Panel = PolPanel<2, 4, 4, 2, true, 1, 2, 4>;    // 256 x 256 tile, 8 waves of 128 x 64
-using H16Panel = PolPanel<2, 4, 4, 2, false, 1, 2, 4>;
+// 256 x 256 tile, 8 waves of 128 x 64, 64-row epilogue passes
+using BF3Panel = PolPanel<2, 4, 4, 2, true, 1, 2, 2>;
+using H16Panel = PolPanel<2, 4, 4, 2, false, 1, 2, 2>;
 
 template <class Q>
 hipError_t launch_panel(const GemmParams& host, const GemmParams* dev, hipStream_t s) {

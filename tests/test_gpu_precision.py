@@ -44,7 +44,8 @@ def run(ns, A, k, method, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32_acc64", "split_bf16", "f16_scaled"])
-@pytest.mark.parametrize("method", ["binary", "radix9", "quinary", "radix15", "radix9_resid", "hensel"])
+@pytest.mark.parametrize("method", ["binary", "radix9", "quinary", "radix15", "radix9_resid", "hensel",
+                                    "radix15c", "mixed"])
 @pytest.mark.parametrize("n", [64, 300])
 def test_mixed_precision_parity(ns, method, dtype, n):
     w = workloads.symmetric(n, 0.9, 200 + n)
@@ -112,3 +113,16 @@ def test_mixed_any_k_precision_forms(ns, dtype, n):
         say(f"   k={k} rel err {err:.3e}")
         assert err < TOL[dtype], (k, err)
         assert rep["gemms_performed"] == orep["products"] and rep["k_eff"] == k
+
+
+@pytest.mark.parametrize("dtype", ["split_bf16", "f16_scaled"])
+def test_panel_path_with_padding(ns, dtype):
+    """n = 2100 pads to 2304: the 16-bit panel engines on a padded matrix
+    (the padding block must stay exactly zero through every product)."""
+    w = workloads.symmetric(2100, 0.9, 31)
+    got, rep = run(ns, w.A, 81, "radix9", dtype)
+    assert rep["n_internal"] == 2304
+    ref = series.spectral_form(w.Q, w.lam, 81, cols=np.arange(0, 2100, 101))
+    err = series.rel_fro(got[:, 0:2100:101], ref)
+    say(f"   sampled rel err {err:.3e}")
+    assert err < TOL[dtype]
