@@ -99,11 +99,8 @@ __device__ __forceinline__ void store_vec(void* p, int f64, size_t idx, double (
 // Apply the affine epilogue to VEC consecutive product values c[] at
 // (row, col .. col + VEC - 1).  Every loop has a compile-time trip count so
 // the kernel-argument struct is only ever indexed statically.
-template <int VEC, bool AMAXO = false>
-__device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, const double (&c)[VEC],
-                                        EpiStateT<AMAXO>& st) {
-  const size_t idx = (size_t)row * p.ld + col;
-  double z[kMaxZ][VEC];
+template <int VEC>
+__device__ __forceinline__ void epi_load(const GemmParams& p, size_t idx, double (&z)[kMaxZ][VEC]) {
 #pragma unroll
   for (int i = 0; i < kMaxZ; ++i) {
     if (i < p.nz) load_vec<VEC>(p.Z[i], p.zf64[i], idx, z[i]);
@@ -111,6 +108,12 @@ __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, c
 #pragma unroll
       for (int e = 0; e < VEC; ++e) z[i][e] = 0.0;
   }
+}
+
+template <int VEC, bool AMAXO>
+__device__ __forceinline__ void epi_apply(const GemmParams& p, int row, int col, size_t idx,
+                                          const double (&c)[VEC], const double (&z)[kMaxZ][VEC],
+                                          EpiStateT<AMAXO>& st) {
 #pragma unroll
   for (int o = 0; o < kMaxOut; ++o) {
     if (o >= p.no) break;
@@ -136,6 +139,28 @@ __device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, c
       }
     }
   }
+}
+
+template <int VEC, bool AMAXO = false>
+__device__ __forceinline__ void epi_vec(const GemmParams& p, int row, int col, const double (&c)[VEC],
+                                        EpiStateT<AMAXO>& st) {
+  const size_t idx = (size_t)row * p.ld + col;
+  double z[kMaxZ][VEC];
+  epi_load<VEC>(p, idx, z);
+  epi_apply<VEC, AMAXO>(p, row, col, idx, c, z, st);
+}
+
+// Two vectors of the general (mixed-type) epilogue, loads first.
+template <int VEC, bool AMAXO = false>
+__device__ __forceinline__ void epi_vec_pair(const GemmParams& p, int row0, int col0,
+                                             const double (&c0)[VEC], int row1, int col1,
+                                             const double (&c1)[VEC], EpiStateT<AMAXO>& st) {
+  const size_t i0 = (size_t)row0 * p.ld + col0, i1 = (size_t)row1 * p.ld + col1;
+  double z0[kMaxZ][VEC], z1[kMaxZ][VEC];
+  epi_load<VEC>(p, i0, z0);
+  epi_load<VEC>(p, i1, z1);
+  epi_apply<VEC, AMAXO>(p, row0, col0, i0, c0, z0, st);
+  epi_apply<VEC, AMAXO>(p, row1, col1, i1, c1, z1, st);
 }
 
 // The same epilogue when every Z input and every output is FP32: float
@@ -691,12 +716,22 @@ __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmPa
         }
       }
     } else {
-      for (int v = tid; v < PROWS * VPR; v += P::THREADS) {
+      for (int v = tid; v < PROWS * VPR; v += 2 * P::THREADS) {
         const int r = v / VPR, cv = (v % VPR) * VEC;
         double c[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * CPITCH + cv + e];
-        epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+        const int v2 = v + P::THREADS;
+        if (v2 < PROWS * VPR) {
+          const int r2 = v2 / VPR, cv2 = (v2 % VPR) * VEC;
+          double c2[VEC];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) c2[e] = (double)C[r2 * CPITCH + cv2 + e];
+          epi_vec_pair<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, row0 + pass * PROWS + r2,
+                            col0 + cv2, c2, st);
+        } else {
+          epi_vec<VEC>(p, row0 + pass * PROWS + r, col0 + cv, c, st);
+        }
       }
     }
     __syncthreads();
