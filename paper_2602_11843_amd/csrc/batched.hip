@@ -208,8 +208,10 @@ __device__ void one_matrix(const BatchArgs& a, int m, float* slot, float* smem) 
 
 using Small = PolF32<2, 2, 2, 2>;     // 64 x 64 tiles for n <= 64
 
-template <class Big>
-__global__ __launch_bounds__(kThreads) void batched_kernel(const BatchArgs a) {
+// MINB: workgroups per CU the register allocation must allow (the compiler
+// caps the registers accordingly; measured per tile, see kBigMinBlocks)
+template <class Big, int MINB>
+__global__ __launch_bounds__(kThreads, MINB) void batched_kernel(const BatchArgs a) {
   constexpr int E1 = tile_smem_elems<Big>(), E2 = tile_smem_elems<Small>();
   __shared__ __align__(16) float smem[E1 > E2 ? E1 : E2];
   __shared__ unsigned s_ticket;
@@ -252,12 +254,19 @@ constexpr int kNumBig = 3;
 using Big0 = PolF32<2, 2, 4, 4>;
 using Big1 = PolF32<2, 2, 2, 4>;
 using Big2 = PolF32<2, 2, 4, 2>;
+// Register caps (as resident workgroups per CU the allocation must allow),
+// measured on the 2048-matrix workload launched two per CU: the 128 x 128 tile
+// takes 2.50 ms compiled for three per CU (168 registers, 512 bytes of spill),
+// 2.91 ms for four, 2.99 ms for two (no spill) and 3.81 ms uncapped (316
+// registers: one per CU).  The 64 x 128 and 128 x 64 tiles are fastest uncapped
+// (2.67 and 2.78 ms).
+constexpr int kMinB0 = 3, kMinB1 = 1, kMinB2 = 1;
 
 void launch_batched(const Config& c, int grid, const BatchArgs& a, hipStream_t s) {
   switch (c.big) {
-    case 0: hipLaunchKernelGGL(batched_kernel<Big0>, dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(batched_kernel<Big1>, dim3(grid), dim3(kThreads), 0, s, a); break;
-    default: hipLaunchKernelGGL(batched_kernel<Big2>, dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((batched_kernel<Big0, kMinB0>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((batched_kernel<Big1, kMinB1>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((batched_kernel<Big2, kMinB2>), dim3(grid), dim3(kThreads), 0, s, a); break;
   }
 }
 
@@ -265,9 +274,9 @@ int max_resident(const Config& c, int* out) {
   int per = 0;
   hipError_t e;
   switch (c.big) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big0>, kThreads, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big1>, kThreads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big2>, kThreads, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big0, kMinB0>, kThreads, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big1, kMinB1>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big2, kMinB2>, kThreads, 0); break;
   }
   if (e != hipSuccess) return batch_fail(NS_ERR_HIP, "occupancy query failed");
   *out = per;
