@@ -644,6 +644,9 @@ __device__ __forceinline__ void tile_mainloop_dma(const typename P::T* __restric
   constexpr int S = P::DMA_STAGES;
   constexpr int PER_CHUNK = DmaPlan<P>::NA + DmaPlan<P>::NB;   // this wave's loads per chunk
   static_assert(S == 2 || S == 3, "two or three LDS stages");
+  // every load instruction copies one whole 1 KB Y-tile row: any other tile
+  // shape would read past the matrix and write past the LDS buffers
+  static_assert(DmaShape<P>::OK, "tile shape unsupported by the direct-to-LDS k-loop");
   // buffer b: X tile at smem + b * A_SZ, Y tile at smem + S * A_SZ + b * B_SZ
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / P::NWN, wn = wave % P::NWN;
