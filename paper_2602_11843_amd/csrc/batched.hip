@@ -151,25 +151,21 @@ __device__ void one_matrix(const BatchArgs& a, int m, float* slot, float* smem) 
       t = B; B = B2; B2 = t;
       continue;
     }
-    {   // radix-9: U = B^2 with the next products' operands formed in its epilogue
+    {   // radix-9: U = B^2, and the next product's operand B + 2U
       GemmParams e = ep0(np, a.nonfinite);
       ep_z(e, B);
       ep_out(e, U, 1.0);
       ep_out(e, X1, 2.0, 1.0);
-      ep_out(e, Pm, 2.0, 3.0 / 20.0);
-      ep_out(e, Q, -1.0 / 8.0, 11.0 / 40.0);
-      ep_out(e, T, 767.0 / 800.0, 1.0);
       wg_product<P>(B, B, np, e, smem);
     }
     __syncthreads();
-    {   // V = U (B + 2U)
+    {   // V = U (B + 2U); P, Q and T - W formed from V, B and U
       GemmParams e = ep0(np, a.nonfinite);
-      ep_z(e, Pm);
-      ep_z(e, Q);
-      ep_z(e, T);
-      ep_out(e, Pm, 1.0, 1.0);
-      ep_out(e, Q, 0.25, 0, 1.0);
-      ep_out(e, T, 15.0 / 32.0, 0, 0, 1.0);
+      ep_z(e, B);
+      ep_z(e, U);
+      ep_out(e, Pm, 1.0, 3.0 / 20.0, 2.0);
+      ep_out(e, Q, 0.25, 11.0 / 40.0, -1.0 / 8.0);
+      ep_out(e, T, 15.0 / 32.0, 1.0, 767.0 / 800.0);
       wg_product<P>(U, X1, np, e, smem);
     }
     __syncthreads();
