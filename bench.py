@@ -130,8 +130,9 @@ def cpu_oracle_sample(fn, label, flops):
 
 def measured_traffic(summary="pmc_product_f64_large_symmetric.md"):
     """HBM-side bytes per launch of the FP64 product kernel from the committed
-    rocprofv3 counter summary, or None once the kernel source has changed
-    since the counters were taken (the summary records a source hash)."""
+    rocprofv3 counter summary, or None once the kernel source or the product
+    schedule (which sets each launch's epilogue) has changed since the
+    counters were taken (the summary records a source hash)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", summary)
@@ -143,7 +144,7 @@ def measured_traffic(summary="pmc_product_f64_large_symmetric.md"):
                 if len(parts) == 2 and parts[0] in ("source_sha256_16", "traffic_bytes_per_launch"):
                     vals[parts[0]] = parts[1]
         h = hashlib.sha256()
-        for f in ("gemm_device.h", "gemm.hip"):
+        for f in ("gemm_device.h", "gemm.hip", "ns.cpp"):
             with open(os.path.join(root, "paper_2602_11843_amd", "csrc", f), "rb") as fh:
                 h.update(fh.read())
         if vals.get("source_sha256_16") != h.hexdigest()[:16]:

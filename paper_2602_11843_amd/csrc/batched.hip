@@ -77,7 +77,10 @@ __device__ __forceinline__ void wg_product(const float* X, const float* Y, int n
     const int row0 = (t / tn_count) * P::BM, col0 = (t % tn_count) * P::BN;
     typename P::Acc acc;
     P::zero(acc);
-    tile_mainloop<P>(X, Y, np, np, row0, col0, smem, acc);
+    if constexpr (DmaShape<P>::OK)        // 1 KB tile rows: np == BN, so rows stay in the slot
+      tile_mainloop_dma<P>(X, Y, np, np, row0, col0, smem, acc);
+    else
+      tile_mainloop<P>(X, Y, np, np, row0, col0, smem, acc);
     tile_epilogue<P, true>(acc, ep, row0, col0, smem, st);   // all slot matrices are FP32
   }
   publish_stats<kThreads>(ep, st, reinterpret_cast<double*>(smem));
@@ -111,8 +114,10 @@ __device__ __forceinline__ void ep_out(GemmParams& p, float* ptr, double a, doub
 // The schedule of one matrix on its slot (increment form of the updates, as
 // in the single-matrix path):
 //   radix-9 (Thm 3.1 in the telescoping update), binary splitting, naive Horner.
+// Forced inline: each tile's instance is called from several kernels, and a
+// call (measured) doubles the 128 x 128 kernel's private memory and its time.
 template <class P>
-__device__ void one_matrix(const BatchArgs& a, int m, float* slot, float* smem) {
+__device__ __forceinline__ void one_matrix(const BatchArgs& a, int m, float* slot, float* smem) {
   const int n = a.nn[m];
   const int np = n <= 64 ? 64 : (n + 127) / 128 * 128;
   const size_t mat = (size_t)np * np;
@@ -203,12 +208,22 @@ __device__ void one_matrix(const BatchArgs& a, int m, float* slot, float* smem) 
 }
 
 using Small = PolF32<2, 2, 2, 2>;     // 64 x 64 tiles for n <= 64
+// 128 x 256 tiles with the direct-to-LDS k-loop for n in (128, 256]: the slot
+// is padded to 256 there, so a tile row is one whole 1 KB slot row
+using Wide = PolF32<2, 2, 4, 8>;
+static_assert(Wide::BN == kMaxBatchN && DmaShape<Wide>::OK, "wide tile spans a padded slot row");
+
+template <class A, class B>
+constexpr int max_smem() {
+  return tile_smem_elems<A>() > tile_smem_elems<B>() ? tile_smem_elems<A>() : tile_smem_elems<B>();
+}
 
 // MINB: workgroups per CU the register allocation must allow (the compiler
-// caps the registers accordingly; measured per tile, see kBigMinBlocks)
-template <class Big, int MINB>
+// caps the registers accordingly; measured per tile, see kMinB0).  WIDE: the
+// matrices with n > 128 use the Wide tile instead of Big.
+template <class Big, int MINB, bool WIDE>
 __global__ __launch_bounds__(kThreads, MINB) void batched_kernel(const BatchArgs a) {
-  constexpr int E1 = tile_smem_elems<Big>(), E2 = tile_smem_elems<Small>();
+  constexpr int E1 = max_smem<Big, Small>(), E2 = WIDE ? tile_smem_elems<Wide>() : 0;
   __shared__ __align__(16) float smem[E1 > E2 ? E1 : E2];
   __shared__ unsigned s_ticket;
   float* slot = a.work + (size_t)blockIdx.x * kSlotMats * kMaxBatchN * kMaxBatchN;
@@ -220,6 +235,7 @@ __global__ __launch_bounds__(kThreads, MINB) void batched_kernel(const BatchArgs
     if (t >= (unsigned)a.batch) break;
     const int m = a.order[t];
     if (a.nn[m] <= 64) one_matrix<Small>(a, m, slot, smem);
+    else if (WIDE && a.nn[m] > 128) one_matrix<Wide>(a, m, slot, smem);
     else one_matrix<Big>(a, m, slot, smem);
   }
   if (threadIdx.x == 0) {
@@ -244,8 +260,8 @@ struct Config {
   int big;          // index into kBigNames
   int per_cu;       // resident workgroups per CU to launch
 };
-const char* kBigNames[] = {"128x128", "64x128", "128x64"};
-constexpr int kNumBig = 3;
+const char* kBigNames[] = {"128x128", "64x128", "128x64", "128x128+128x256"};
+constexpr int kNumBig = 4;
 
 using Big0 = PolF32<2, 2, 4, 4>;
 using Big1 = PolF32<2, 2, 2, 4>;
@@ -257,12 +273,16 @@ using Big2 = PolF32<2, 2, 4, 2>;
 // registers: one per CU).  The 64 x 128 and 128 x 64 tiles are fastest uncapped
 // (2.67 and 2.78 ms).
 constexpr int kMinB0 = 3, kMinB1 = 1, kMinB2 = 1;
+// with the Wide tile (128 accumulator registers per lane) the kernel is
+// compiled for two workgroups per CU, which its 66.5 KB of LDS also sets
+constexpr int kMinBW = 2;
 
 void launch_batched(const Config& c, int grid, const BatchArgs& a, hipStream_t s) {
   switch (c.big) {
-    case 0: hipLaunchKernelGGL((batched_kernel<Big0, kMinB0>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((batched_kernel<Big1, kMinB1>), dim3(grid), dim3(kThreads), 0, s, a); break;
-    default: hipLaunchKernelGGL((batched_kernel<Big2, kMinB2>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((batched_kernel<Big0, kMinB0, false>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((batched_kernel<Big1, kMinB1, false>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((batched_kernel<Big2, kMinB2, false>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((batched_kernel<Big0, kMinBW, true>), dim3(grid), dim3(kThreads), 0, s, a); break;
   }
 }
 
@@ -270,9 +290,10 @@ int max_resident(const Config& c, int* out) {
   int per = 0;
   hipError_t e;
   switch (c.big) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big0, kMinB0>, kThreads, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big1, kMinB1>, kThreads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big2, kMinB2>, kThreads, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big0, kMinB0, false>, kThreads, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big1, kMinB1, false>, kThreads, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big2, kMinB2, false>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<Big0, kMinBW, true>, kThreads, 0); break;
   }
   if (e != hipSuccess) return batch_fail(NS_ERR_HIP, "occupancy query failed");
   *out = per;

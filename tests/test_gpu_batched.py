@@ -1,6 +1,7 @@
 """GPU parity of the batched form (one persistent launch, cached HIP graph)
 against the oracle and against the per-matrix launch loop."""
 
+import json
 import sys
 
 import numpy as np
@@ -143,6 +144,39 @@ def test_autotune_then_evaluate(ns, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(got, ref)
     assert (tmp_path / "tune.jsonl").read_text().count("\"big\"") == 1
+    h.close()
+
+
+def hist_key(ns_):
+    """The batched path's key for a batch's n histogram (ascending n)."""
+    vals, counts = np.unique(ns_, return_counts=True)
+    return "".join(f"{v}:{c}," for v, c in zip(vals, counts))
+
+
+# tile configurations of the persistent kernel: 128x128, 64x128, 128x64, and
+# 128x128 with 128x256 direct-to-LDS tiles for n > 128
+@pytest.mark.parametrize("big", [0, 1, 2, 3])
+def test_every_tile_config(ns, tmp_path, monkeypatch, big):
+    """Each configuration the autotuner may pick, forced through the tuning
+    file: bit-identical to the per-matrix launch loop and within FP32
+    rounding of the oracle, for every method."""
+    mats = mixed_batch(6)
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    path = tmp_path / "tune.jsonl"
+    path.write_text(json.dumps({"hist": hist_key(ns_), "big": big, "per_cu": 2}) + "\n")
+    monkeypatch.setenv("NS_TUNE_CACHE", str(path))
+    h = ns.Handle(0)
+    for method, k in (("radix9", 81), ("binary", 81), ("naive", 12)):
+        say(f"[gpu] batched tile config {big} {method} batch={len(mats)}")
+        got = ns.ns_eval_batched(A, offd, nd, nh, k, method, "f32", handle=h)
+        ref = ns.ns_eval_batched_loop(A, torch.from_numpy(offs), nh, k, method, "f32", handle=h)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), method
+        worst = 0.0
+        for M, G in zip(mats, unpack(got.cpu().numpy(), offs, ns_)):
+            o, _ = series.evaluate(M.astype(np.float32).astype(np.float64), k, method)
+            worst = max(worst, series.rel_fro(G, o))
+        assert worst < 1e-5, (method, worst)
     h.close()
 
 
