@@ -37,6 +37,117 @@ hipError_t launch_low(const GemmParams& host, const GemmParams* dev, hipStream_t
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Latency-bound FP64 sizes (kSplitKMin <= n <= kSplitKMax): a 16 x 16 output
+// tile per workgroup, so that n = 256 gives 256 workgroups (the 32 x 32 tile
+// gives 64), with the k range split over the four waves: wave w takes the
+// 16-wide k-chunks w, w + 4, ... and loads its operands straight from global
+// memory into the v_mfma_f64_4x4x4f64 operand layout, SK_CB chunks per batch
+// with the next batch in flight.  A chunk is 16 MFMAs per wave, far less than
+// a load's latency, so an LDS-staged k-loop waits on memory once per chunk;
+// here a wave waits about once per batch.  The four partial tiles are summed
+// in LDS in wave order before the shared epilogue.  (Above n = 256 the 16 x 16
+// tiles re-read X and Y too often: 1.7x slower than 32 x 32 at n = 384.)
+// Operand lanes (see PolF64): A_b[i][k] at i = l & 3, k = 4 b + (l >> 4);
+// B_b[k][j] at j = l & 3; block b = (l >> 2) & 3.
+// ---------------------------------------------------------------------------
+constexpr int SK_TILE = 16, SK_WAVES = 4, SK_CB = 4;
+constexpr int kSplitKMin = 160, kSplitKMax = 256;
+
+__global__ __launch_bounds__(64 * SK_WAVES, 2) void gemm_f64_splitk_kernel(const MainArgs args) {
+  __shared__ double part[SK_WAVES][SK_TILE][SK_TILE + 2];
+  __shared__ double stats[(3 + kMaxOut) * SK_WAVES];
+  const int tiles = args.n / SK_TILE;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles, tiles, tm, tn);
+  const int row0 = tm * SK_TILE, col0 = tn * SK_TILE, ld = args.ld;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane & 3, kk = 4 * ((lane >> 2) & 3) + (lane >> 4);
+  const double* __restrict__ X = static_cast<const double*>(args.X) + (size_t)(row0 + q) * ld + kk;
+  const double* __restrict__ Y = static_cast<const double*>(args.Y) + (size_t)kk * ld + col0 + q;
+  const int nk = args.n / 16;
+  const int mine = nk > w ? (nk - w + SK_WAVES - 1) / SK_WAVES : 0;   // this wave's chunks
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // operands of batch bt; slots past the wave's last chunk re-read that chunk
+  // and are not multiplied
+  auto load = [&](int bt, double (&a)[SK_CB][4], double (&b)[SK_CB][4]) {
+#pragma unroll
+    for (int j = 0; j < SK_CB; ++j) {
+      const int c = w + SK_WAVES * min(bt * SK_CB + j, mine - 1);
+      const size_t k = (size_t)16 * c;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) a[j][f] = X[(size_t)4 * f * ld + k];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) b[j][f] = Y[k * ld + 4 * f];
+    }
+  };
+  if (mine > 0) {
+    const int nb = (mine + SK_CB - 1) / SK_CB;
+    double a0[SK_CB][4], b0[SK_CB][4];
+    load(0, a0, b0);
+    for (int bt = 0; bt < nb; ++bt) {
+      double a1[SK_CB][4], b1[SK_CB][4];
+      load(min(bt + 1, nb - 1), a1, b1);
+#pragma unroll
+      for (int j = 0; j < SK_CB; ++j) {
+        if (bt * SK_CB + j >= mine) break;        // wave-uniform
+#pragma unroll
+        for (int fi = 0; fi < 4; ++fi)
+#pragma unroll
+          for (int fj = 0; fj < 4; ++fj)
+            acc[fi][fj] = __builtin_amdgcn_mfma_f64_4x4x4f64(a0[j][fi], b0[j][fj], acc[fi][fj], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < SK_CB; ++j)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          a0[j][f] = a1[j][f];
+          b0[j][f] = b1[j][f];
+        }
+    }
+  }
+  // sum the four k-slices of each fragment; block-lane b then writes the
+  // fragments whose index is b mod 4 (result lane: row l >> 4, column l & 3)
+  const int bb = (lane >> 2) & 3, ri = lane >> 4, cj = lane & 3;
+#pragma unroll
+  for (int fi = 0; fi < 4; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 4; ++fj) {
+      double x = acc[fi][fj];
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      if (((fi * 4 + fj) & 3) == bb) part[w][4 * fi + ri][4 * fj + cj] = x;
+    }
+  __syncthreads();
+  const GemmParams& p = *args.epi;
+  EpiState st{0.0, 0.f, 0};
+  if (threadIdx.x < SK_TILE * SK_TILE / 2) {
+    const int r = threadIdx.x / (SK_TILE / 2), cv = (threadIdx.x % (SK_TILE / 2)) * 2;
+    double c[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      double v = part[0][r][cv + e];
+#pragma unroll
+      for (int ww = 1; ww < SK_WAVES; ++ww) v += part[ww][r][cv + e];
+      c[e] = v;
+    }
+    epi_vec<2>(p, row0 + r, col0 + cv, c, st);
+  }
+  publish_stats<64 * SK_WAVES>(p, st, stats);
+}
+
+hipError_t launch_splitk(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
+  if (host.n % 32 || host.n > kSplitKMax) return hipErrorInvalidValue;
+  const int t = host.n / SK_TILE;
+  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
+  hipLaunchKernelGGL(gemm_f64_splitk_kernel, dim3(t * t), dim3(64 * SK_WAVES), 0, s, a);
+  return hipGetLastError();
+}
+
 // tile choices
 using F64Big = PolF64<2, 4, 8, 8, 2>;     // 64 x 128 tile, k-chunk 32, 8 waves
 using F64Small = PolF64<2, 2, 4, 4, 1>;   // 32 x 32 tile, k-chunk 16, 4 waves
@@ -63,7 +174,10 @@ int engine_tile(Engine e, int n) {
 
 hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s) {
   switch (e) {
-    case ENG_F64: return host.n >= kBigMin ? launch<F64Big>(host, dev, s) : launch<F64Small>(host, dev, s);
+    case ENG_F64:
+      if (host.n >= kBigMin) return launch<F64Big>(host, dev, s);
+      if (host.n >= kSplitKMin && host.n <= kSplitKMax) return launch_splitk(host, dev, s);
+      return launch<F64Small>(host, dev, s);
     case ENG_F32: return host.n >= kBigMin ? launch<F32Big>(host, dev, s) : launch<F32Small>(host, dev, s);
     // at n >= kPanelMin these engines run from panels (launch_gemm_panels)
     case ENG_BF16X3: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<BF3Small>(host, dev, s);

@@ -84,6 +84,23 @@ def test_small_parity(ns, method, dtype, n):
             assert np.allclose(ln, on, rtol=1e-9, atol=1e-12)
 
 
+# FP64 products at padded n in [160, 256] use the split-K 16 x 16 tile: its
+# lower edge (150 -> 160), ragged tails (200 -> 224, 225 -> 256) and a
+# non-symmetric input, every epilogue shape the schedules use
+@pytest.mark.parametrize("method", ["naive", "binary", "radix9", "radix15c", "radix9_resid", "ternary"])
+@pytest.mark.parametrize("n", [150, 200, 225])
+def test_splitk_range_parity(ns, method, n):
+    w = workloads.gaussian(n, 0.9, 300 + n) if n == 225 else workloads.symmetric(n, 0.9, 300 + n)
+    k = 20 if method == "naive" else 81
+    got, rep = run(ns, w.A, k, method, "f64")
+    ref, orep = series.evaluate(w.A, k, ORACLE_NAME[method])
+    err = series.rel_fro(got, ref)
+    say(f"   rel err {err:.3e}  n_internal {rep['n_internal']}")
+    assert rep["n_internal"] in (160, 224, 256)
+    assert err < TOL["f64"]
+    assert not rep["nonfinite"]
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("method", ["binary", "radix9", "radix15", "radix15c"])
 def test_nonsymmetric_parity(ns, method, dtype):
