@@ -124,16 +124,25 @@ def sampled_cols(n, count, seed=0):
     return np.sort(rng.choice(n, count, replace=False))
 
 
-def cpu_oracle_sample(fn, label, flops):
-    """Time the oracle (test/benchmark infrastructure) on a bounded sample."""
+def cpu_oracle_sample(fn, label, flops, min_seconds=10.0, max_runs=50):
+    """Time the oracle (test/benchmark infrastructure) on a bounded sample:
+    `fn` (worth `flops`) is run until at least min_seconds have passed (at
+    most max_runs times); the rate is the mean over the runs, and the first
+    run's result is returned."""
     thr = blas_threads()
     log(f"[bench] cpu oracle: {label} on {thr} threads")
     t0 = time.perf_counter()
     res = fn()
-    sec = time.perf_counter() - t0
-    log(f"[bench]   cpu {sec:.2f} s")
+    runs = 1
+    while time.perf_counter() - t0 < min_seconds and runs < max_runs:
+        fn()
+        runs += 1
+    total = time.perf_counter() - t0
+    sec = total / runs
+    log(f"[bench]   cpu {runs} run(s), {sec:.2f} s each")
     return res, {"value": round(flops / sec / 1e12, 4), "unit": "TFLOP/s", "cores": thr,
-                 "kind": "oracle", "sample": f"{label} ({sec:.2f} s, {cpu_model()})"}
+                 "kind": "oracle",
+                 "sample": f"{label}: {runs} run(s), {sec:.2f} s each, {total:.1f} s in all ({cpu_model()})"}
 
 
 def measured_traffic(summary="pmc_product_f64_large_symmetric.md"):
