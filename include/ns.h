@@ -191,11 +191,13 @@ int ns_eval_batched_loop(ns_handle* h, const void* A_packed, const int64_t* off_
                          const int32_t* n_host, int32_t batch, int64_t k, int method,
                          int dtype, void* out_packed, hipStream_t stream);
 
-/* Time the batched kernel's candidate tile configurations for the n classes
-   of this batch and keep the fastest per class in the handle (and in the JSON
-   file named by the NS_TUNE_CACHE environment variable, if set).  Same
-   buffer arguments as ns_eval_batched; the contents of out_packed are
-   overwritten.  Returns the number of configurations timed in *n_timed. */
+/* Time every candidate configuration of the batched kernel (tile shapes and
+   resident workgroups per CU) on this batch, radix-9, and keep the fastest
+   for batches with the same histogram of n, in the handle (and in the JSON
+   file named by the NS_TUNE_CACHE environment variable, if set); later
+   ns_eval_batched calls on such batches use it.  Same buffer arguments as
+   ns_eval_batched; the contents of out_packed are overwritten.  Returns the
+   number of configurations timed in *n_timed. */
 int ns_autotune_batched(ns_handle* h, const void* A_packed, const int64_t* off_dev,
                         const int32_t* n_dev, const int32_t* n_host, int32_t batch,
                         int64_t k, void* out_packed, hipStream_t stream,

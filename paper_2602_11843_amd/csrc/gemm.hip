@@ -13,6 +13,9 @@
 // Both stage BM x BK and BK x BN tiles through double-buffered LDS with 16-byte
 // global loads, one barrier per k-chunk, and order workgroups so that the
 // tiles resident on one XCD share rows of X and columns of Y in that XCD's L2.
+// The exception is FP64 at padded n in [160, 256], where a product is
+// latency-bound: gemm_f64_splitk_kernel below splits k over the waves and
+// loads its operands straight into registers.
 #include "gemm_device.h"
 
 namespace ns {
