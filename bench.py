@@ -240,7 +240,7 @@ def bench_large_symmetric(args, torch, ns):
         if ("radix9", d) in res and ("binary", d) in res:
             line[f"radix9_over_binary_speedup_{d}"] = round(res[("binary", d)]["ms"] / res[("radix9", d)]["ms"], 4)
     line["predicted_speedup_by_product_count"] = round(20 / 15, 4)
-    kern = "gemm_kernel<PolF64<2,4,8,8,2>>" if key[1] == "f64" else "gemm_kernel<PolF32<2,2,4,8>>"
+    kern = "gemm_kernel<PolF64M16<2,2,4,4>>" if key[1] == "f64" else "gemm_kernel<PolF32<2,2,4,8>>"
     line["roofline"] = roofline_from_leg(main, n, kern, key[1])
     if line["roofline"] and key == ("radix9", "f64"):
         line["roofline"]["traffic"] = measured_traffic()

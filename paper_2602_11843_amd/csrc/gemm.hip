@@ -5,10 +5,11 @@
 // between products.
 //
 // Engines
-//   FP64: v_mfma_f64_4x4x4f64.  Its four 4x4 blocks are used as four
+//   FP64: v_mfma_f64_16x16x4f64 on 128 x 128 tiles from n = 2048 (four
+//         waves of 64 x 64, two workgroups per CU); below, the 32 x 32 tile
+//         on v_mfma_f64_4x4x4f64, whose four 4x4 blocks are used as four
 //         k-slices of one 4x4 output fragment and summed across lanes once
-//         per tile (measured on gfx950: this instruction sustains ~57 TFLOP/s
-//         against ~44 for the 16x16x4 form).
+//         per tile.
 //   FP32: v_mfma_f32_16x16x4f32.
 // Both stage BM x BK and BK x BN tiles through double-buffered LDS with 16-byte
 // global loads, one barrier per k-chunk, and order workgroups so that the
@@ -152,7 +153,7 @@ hipError_t launch_splitk(const GemmParams& host, const GemmParams* dev, hipStrea
 }
 
 // tile choices
-using F64Big = PolF64<2, 4, 8, 8, 2>;     // 64 x 128 tile, k-chunk 32, 8 waves
+using F64Big = PolF64M16<2, 2, 4, 4>;    // 128 x 128 tile, 16x16x4 MFMA, 4 waves, two per CU
 using F64Small = PolF64<2, 2, 4, 4, 1>;   // 32 x 32 tile, k-chunk 16, 4 waves
 using F32Big = PolF32<2, 2, 4, 8>;     // 128 x 256 tile, 4 waves
 using F32Small = PolF32<2, 2, 2, 2>;   // 64 x 64 tile, 4 waves

@@ -321,6 +321,7 @@ struct PolF64 {
   using T = double;
   static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
   static constexpr int KS = KS_;           // instructions per fragment pair per chunk
+  static constexpr int MINB = 1;
   static constexpr int WTM = 4 * NI, WTN = 4 * NJ;
   static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16 * KS;
   static constexpr int THREADS = 64 * NWM * NWN;
@@ -330,24 +331,13 @@ struct PolF64 {
   static constexpr int APITCH = BK;
   // B reads touch 16 rows KS apart; a pitch of BN + 2 doubles puts rows
   // 2 apart 32 bytes apart in the banks.
-  static constexpr bool SWZ = KS == 2;
   static constexpr int BPITCH = BN + 2;
   // stage the whole tile at once: with one pass per wave-row, a later
   // wave-row would hold its accumulators through the earlier pass's epilogue
   static constexpr int EPI_PASSES = 1;
   static constexpr int DMA_STAGES = 2;    // LDS buffers of the direct-to-LDS k-loop
-  // LDS swizzle of the large tile: 16-byte chunk c of tile row r is stored at
-  // chunk c ^ swz(r); the loaders apply it when they pick each lane's global
-  // chunk.  X rows (256-byte pitch): the four rows of an A read (r & 3 = q)
-  // would otherwise share banks (a 4-way conflict); with the swizzle the A
-  // reads are conflict-free.  Y rows: rows 16 apart move 64 bytes apart.
-  // (Measured on the part: the X swizzle takes the n = 4096 product from 2.78
-  // to 2.54 ms; Y layouts free of every bank conflict, with an unpadded or a
-  // BN + 4 pitch and a three-bit row swizzle, were slower, 2.76 ms.)
-  static __device__ __forceinline__ int a_swz(int r) { return SWZ ? (r & 3) : 0; }
-  static __device__ __forceinline__ int b_swz(int r) {
-    return SWZ ? 4 * ((r >> 4) & 1) : 0;
-  }
+  static __device__ __forceinline__ int a_swz(int) { return 0; }   // no LDS swizzle
+  static __device__ __forceinline__ int b_swz(int) { return 0; }
   struct Acc {
     double v[NI][NJ];
   };
@@ -364,7 +354,7 @@ struct PolF64 {
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int row = wm * WTM + 4 * i + q, col = KS * kk;
-      const double* src = &As[row * APITCH + ((((col >> 1) ^ a_swz(row)) << 1) | (col & 1))];
+      const double* src = &As[row * APITCH + col];
       if constexpr (KS % 2 == 0) {
 #pragma unroll
         for (int s = 0; s < KS; s += 2) {
@@ -384,7 +374,7 @@ struct PolF64 {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int row = KS * kk + s, col = wn * WTN + 4 * j + q;
-        const double bf = Bs[row * BPITCH + ((((col >> 1) ^ b_swz(row)) << 1) | (col & 1))];
+        const double bf = Bs[row * BPITCH + col];
 #pragma unroll
         for (int i = 0; i < NI; ++i)
           acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf, acc.v[i][j], 0, 0, 0);
@@ -416,6 +406,83 @@ struct PolF64 {
 };
 
 // ---------------------------------------------------------------------------
+// FP64 policy on v_mfma_f64_16x16x4f64: one instruction is a 16x16 output
+// fragment times a 4-deep k-slice (1024 FMAs, 64 matrix-core cycles).
+//   A operand A[i][k], i = l&15, k = l>>4;  B operand B[k][j], j = l&15, k = l>>4
+//   result D[4 r + (l>>4)][l&15], r = 0..3 (decoded on the device: rows are
+//   interleaved, unlike the FP32 16x16x4 form's D[4 (l>>4) + r][l&15])
+// As in the FP32 policy the 16-wide k-chunk is permuted: lane group g = l>>4
+// owns k = 4g..4g+3 across the four instructions of a chunk, so its A values
+// are one 32-byte run of the row.  X-tile rows are 128 bytes; 16-byte chunk c
+// of row r is stored at chunk c ^ (r & 7), so the eight rows a 16-byte read
+// serves at once fall on distinct banks.
+// ---------------------------------------------------------------------------
+template <int NWM_, int NWN_, int NI_, int NJ_, int MINB_ = 2>
+struct PolF64M16 {
+  using T = double;
+  static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
+  // workgroups per CU the register allocation must allow: capped at two, the
+  // compiler keeps the accumulators in VGPRs (measured: 2.07 ms per n = 4096
+  // product; uncapped it moves them to AGPRs and takes 2.73 ms)
+  static constexpr int MINB = MINB_;
+  static constexpr int WTM = 16 * NI, WTN = 16 * NJ;
+  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16;
+  static constexpr int THREADS = 64 * NWM * NWN;
+  static constexpr int APITCH = BK;
+  static constexpr int BPITCH = BN + 2;
+  static constexpr int EPI_PASSES = NWM;  // stage one wave-row at a time (bounds the LDS)
+  static constexpr int DMA_STAGES = 2;
+  static __device__ __forceinline__ int a_swz(int r) { return r & 7; }
+  static __device__ __forceinline__ int b_swz(int) { return 0; }
+  struct Acc {
+    d4 v[NI][NJ];
+  };
+  static __device__ __forceinline__ void zero(Acc& a) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) a.v[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  static __device__ __forceinline__ void chunk(const T* __restrict__ As, const T* __restrict__ Bs,
+                                               Acc& acc, int wm, int wn, int lane) {
+    const int q = lane & 15, g = lane >> 4;
+    double af[NI][4];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int row = wm * WTM + 16 * i + q;
+      const double2 t0 = *reinterpret_cast<const double2*>(&As[row * APITCH + ((2 * g) ^ a_swz(row)) * 2]);
+      const double2 t1 = *reinterpret_cast<const double2*>(&As[row * APITCH + ((2 * g + 1) ^ a_swz(row)) * 2]);
+      af[i][0] = t0.x;
+      af[i][1] = t0.y;
+      af[i][2] = t1.x;
+      af[i][3] = t1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double bf[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) bf[j] = Bs[(4 * g + s) * BPITCH + wn * WTN + 16 * j + q];
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j], acc.v[i][j], 0, 0, 0);
+    }
+  }
+  using CT = double;
+  static __device__ __forceinline__ void stage(Acc& acc, int lane, int wn, CT* C, int cpitch) {
+    const int q = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int a = 0; a < NI; ++a)
+#pragma unroll
+      for (int c = 0; c < NJ; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          C[(16 * a + 4 * r + g) * cpitch + wn * WTN + 16 * c + q] = acc.v[a][c][r];
+  }
+};
+
+// ---------------------------------------------------------------------------
 // FP32 policy: v_mfma_f32_16x16x4f32.
 //   A operand A[i][k], i = l&15, k = l>>4;  B operand B[k][j], j = l&15, k = l>>4
 //   result D[4 (l>>4) + r][l&15], r = 0..3
@@ -429,6 +496,7 @@ struct PolF32 {
   static constexpr int WTM = 16 * NI, WTN = 16 * NJ;
   static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16;
   static constexpr int THREADS = 64 * NWM * NWN;
+  static constexpr int MINB = 1;
   static constexpr int APITCH = BK;       // a wave's A reads are one contiguous 1 KB run
   static constexpr int BPITCH = BN + 4;   // the 4 k-rows of a B read land in distinct banks
   static constexpr int EPI_PASSES = NWM;  // stage one wave-row at a time (bounds the LDS)
@@ -742,7 +810,7 @@ __device__ __forceinline__ void tile_epilogue(typename P::Acc& acc, const GemmPa
 }
 
 template <class P>
-__global__ __launch_bounds__(P::THREADS) void gemm_kernel(const MainArgs args) {
+__global__ __launch_bounds__(P::THREADS, P::MINB) void gemm_kernel(const MainArgs args) {
   using T = typename P::T;
   __shared__ __align__(16) T smem[tile_smem_elems<P>()];
   const int tiles_m = args.n / P::BM, tiles_n = args.n / P::BN;
