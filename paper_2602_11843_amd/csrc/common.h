@@ -23,7 +23,7 @@ struct EpiOut {
 
 // Operand storage / arithmetic of a product launch.
 enum Engine : int {
-  ENG_F64 = 0,        // double operands, FP64 MFMA 4x4x4
+  ENG_F64 = 0,        // double operands, FP64 MFMA (16x16x4; 4x4x4 in the split-K kernel)
   ENG_F32 = 1,        // float operands, FP32 MFMA 16x16x4
   ENG_BF16X3 = 2,     // float operands split to bf16 hi/lo, 3 BF16 MFMA products
   ENG_F16S = 3,       // float operands scaled by 2^-e and rounded to fp16, 1 FP16 MFMA product

@@ -5,11 +5,11 @@
 // between products.
 //
 // Engines
-//   FP64: v_mfma_f64_16x16x4f64 on 128 x 128 tiles from n = 2048 (four
-//         waves of 64 x 64, two workgroups per CU); below, the 32 x 32 tile
-//         on v_mfma_f64_4x4x4f64, whose four 4x4 blocks are used as four
-//         k-slices of one 4x4 output fragment and summed across lanes once
-//         per tile.
+//   FP64: v_mfma_f64_16x16x4f64: 128 x 128 tiles from n = 2048 (four waves
+//         of 64 x 64, two workgroups per CU), 32 x 32 tiles below (four waves
+//         of 16 x 16, four workgroups per CU), except the split-K kernel for
+//         padded n in [160, 256].  v_mfma_f64_4x4x4f64 (its four 4x4 blocks
+//         as four k-slices of one fragment) serves the split-K kernel.
 //   FP32: v_mfma_f32_16x16x4f32.
 // Both stage BM x BK and BK x BN tiles through double-buffered LDS with 16-byte
 // global loads, one barrier per k-chunk, and order workgroups so that the
@@ -154,7 +154,7 @@ hipError_t launch_splitk(const GemmParams& host, const GemmParams* dev, hipStrea
 
 // tile choices
 using F64Big = PolF64M16<2, 2, 4, 4>;    // 128 x 128 tile, 16x16x4 MFMA, 4 waves, two per CU
-using F64Small = PolF64<2, 2, 4, 4, 1>;   // 32 x 32 tile, k-chunk 16, 4 waves
+using F64Small = PolF64M16<2, 2, 1, 1, 4>;   // 32 x 32 tile, 16x16x4 MFMA, 4 waves, four per CU
 using F32Big = PolF32<2, 2, 4, 8>;     // 128 x 256 tile, 4 waves
 using F32Small = PolF32<2, 2, 2, 2>;   // 64 x 64 tile, 4 waves
 

@@ -307,105 +307,6 @@ __device__ __forceinline__ void publish_stats(const GemmParams& p, EpiStateT<AMA
 }
 
 // ---------------------------------------------------------------------------
-// FP64 policy: v_mfma_f64_4x4x4f64.
-// Lane l of the instruction: block b = (l>>2)&3, and
-//   A operand  A_b[i][k], i = l&3,  k = l>>4
-//   B operand  B_b[k][j], j = l&3,  k = l>>4
-//   result     D_b[i][j], i = l>>4, j = l&3
-// (decoded on the device).  The four blocks take four disjoint k-slices, so
-// one instruction advances a 4x4 output fragment by 16 k; the block partial
-// sums are added across lanes once per tile.
-// ---------------------------------------------------------------------------
-template <int NWM_, int NWN_, int NI_, int NJ_, int KS_>
-struct PolF64 {
-  using T = double;
-  static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
-  static constexpr int KS = KS_;           // instructions per fragment pair per chunk
-  static constexpr int MINB = 1;
-  static constexpr int WTM = 4 * NI, WTN = 4 * NJ;
-  static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16 * KS;
-  static constexpr int THREADS = 64 * NWM * NWN;
-  // Lane slot kk = 4 b + k (0..15) owns chunk columns KS*kk .. KS*kk + KS - 1,
-  // one per instruction step s: its A values for all steps are one
-  // contiguous KS-double read, and the A reads of a wave cover 4 full rows.
-  static constexpr int APITCH = BK;
-  // B reads touch 16 rows KS apart; a pitch of BN + 2 doubles puts rows
-  // 2 apart 32 bytes apart in the banks.
-  static constexpr int BPITCH = BN + 2;
-  // stage the whole tile at once: with one pass per wave-row, a later
-  // wave-row would hold its accumulators through the earlier pass's epilogue
-  static constexpr int EPI_PASSES = 1;
-  static constexpr int DMA_STAGES = 2;    // LDS buffers of the direct-to-LDS k-loop
-  static __device__ __forceinline__ int a_swz(int) { return 0; }   // no LDS swizzle
-  static __device__ __forceinline__ int b_swz(int) { return 0; }
-  struct Acc {
-    double v[NI][NJ];
-  };
-  static __device__ __forceinline__ void zero(Acc& a) {
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) a.v[i][j] = 0.0;
-  }
-  static __device__ __forceinline__ void chunk(const T* __restrict__ As, const T* __restrict__ Bs,
-                                               Acc& acc, int wm, int wn, int lane) {
-    const int q = lane & 3, kk = 4 * ((lane >> 2) & 3) + (lane >> 4);
-    double af[NI][KS];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int row = wm * WTM + 4 * i + q, col = KS * kk;
-      const double* src = &As[row * APITCH + col];
-      if constexpr (KS % 2 == 0) {
-#pragma unroll
-        for (int s = 0; s < KS; s += 2) {
-          const double2 t = *reinterpret_cast<const double2*>(src + s);
-          af[i][s] = t.x;
-          af[i][s + 1] = t.y;
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < KS; ++s) af[i][s] = src[s];
-      }
-    }
-    // B fragments are consumed one column block at a time, so only the A
-    // fragments and one B value are live next to the accumulators
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int row = KS * kk + s, col = wn * WTN + 4 * j + q;
-        const double bf = Bs[row * BPITCH + col];
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-          acc.v[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf, acc.v[i][j], 0, 0, 0);
-      }
-  }
-  // Sum the four k-slices (lanes differing in bits 2-3), then write this
-  // wave's WTM x WTN results into the staging tile C (row pitch CPITCH, rows
-  // relative to the wave's first row).
-  using CT = double;
-  static __device__ __forceinline__ void stage(Acc& acc, int lane, int wn, CT* C, int cpitch) {
-    const int i = lane >> 4, b = (lane >> 2) & 3, j = lane & 3;
-#pragma unroll
-    for (int a = 0; a < NI; ++a)
-#pragma unroll
-      for (int c = 0; c < NJ; ++c) {
-        double x = acc.v[a][c];
-        x += __shfl_xor(x, 4);
-        x += __shfl_xor(x, 8);
-        acc.v[a][c] = x;
-      }
-    // the four block-lanes now hold the same sums; block-lane b writes the
-    // fragments whose index is b mod 4
-#pragma unroll
-    for (int a = 0; a < NI; ++a)
-#pragma unroll
-      for (int c = 0; c < NJ; ++c)
-        if (((a * NJ + c) & 3) == b) C[(4 * a + i) * cpitch + wn * WTN + 4 * c + j] = acc.v[a][c];
-  }
-};
-
-// ---------------------------------------------------------------------------
 // FP64 policy on v_mfma_f64_16x16x4f64: one instruction is a 16x16 output
 // fragment times a 4-deep k-slice (1024 FMAs, 64 matrix-core cycles).
 //   A operand A[i][k], i = l&15, k = l>>4;  B operand B[k][j], j = l&15, k = l>>4
@@ -417,7 +318,7 @@ struct PolF64 {
 // of row r is stored at chunk c ^ (r & 7), so the eight rows a 16-byte read
 // serves at once fall on distinct banks.
 // ---------------------------------------------------------------------------
-template <int NWM_, int NWN_, int NI_, int NJ_, int MINB_ = 2>
+template <int NWM_, int NWN_, int NI_, int NJ_, int MINB_ = 2, int SWZ_ = 0, int BPAD_ = 2>
 struct PolF64M16 {
   using T = double;
   static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
@@ -429,10 +330,10 @@ struct PolF64M16 {
   static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16;
   static constexpr int THREADS = 64 * NWM * NWN;
   static constexpr int APITCH = BK;
-  static constexpr int BPITCH = BN + 2;
+  static constexpr int BPITCH = BN + BPAD_;
   static constexpr int EPI_PASSES = NWM;  // stage one wave-row at a time (bounds the LDS)
   static constexpr int DMA_STAGES = 2;
-  static __device__ __forceinline__ int a_swz(int r) { return r & 7; }
+  static __device__ __forceinline__ int a_swz(int r) { return SWZ_ == 0 ? (r & 7) : ((r >> 1) & 7); }
   static __device__ __forceinline__ int b_swz(int) { return 0; }
   struct Acc {
     d4 v[NI][NJ];
