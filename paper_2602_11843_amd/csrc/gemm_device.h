@@ -318,7 +318,7 @@ __device__ __forceinline__ void publish_stats(const GemmParams& p, EpiStateT<AMA
 // of row r is stored at chunk c ^ (r & 7), so the eight rows a 16-byte read
 // serves at once fall on distinct banks.
 // ---------------------------------------------------------------------------
-template <int NWM_, int NWN_, int NI_, int NJ_, int MINB_ = 2, int SWZ_ = 0, int BPAD_ = 2>
+template <int NWM_, int NWN_, int NI_, int NJ_, int MINB_ = 2>
 struct PolF64M16 {
   using T = double;
   static constexpr int NWM = NWM_, NWN = NWN_, NI = NI_, NJ = NJ_;
@@ -330,10 +330,10 @@ struct PolF64M16 {
   static constexpr int BM = NWM * WTM, BN = NWN * WTN, BK = 16;
   static constexpr int THREADS = 64 * NWM * NWN;
   static constexpr int APITCH = BK;
-  static constexpr int BPITCH = BN + BPAD_;
+  static constexpr int BPITCH = BN + 2;
   static constexpr int EPI_PASSES = NWM;  // stage one wave-row at a time (bounds the LDS)
   static constexpr int DMA_STAGES = 2;
-  static __device__ __forceinline__ int a_swz(int r) { return SWZ_ == 0 ? (r & 7) : ((r >> 1) & 7); }
+  static __device__ __forceinline__ int a_swz(int r) { return r & 7; }
   static __device__ __forceinline__ int b_swz(int) { return 0; }
   struct Acc {
     d4 v[NI][NJ];
