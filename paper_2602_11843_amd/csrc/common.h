@@ -88,4 +88,20 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
 // max-abs of a float matrix into *amax (float bits), atomically.
 hipError_t launch_amax(const float* x, size_t count, unsigned* amax, hipStream_t s);
 
+// Up to kMaxFills independent fills in ONE launch (the grid is split between
+// them): the scalar-block reset, copies-in and identities that start a call
+// write distinct buffers and read only the caller's A.
+enum FillKind : int { FILL_ZERO = 0, FILL_PAD, FILL_IDENTITY };
+struct Fill {
+  int kind;                 // FillKind
+  int src_f64, dst_f64;     // element types (PAD: both; IDENTITY: dst)
+  int n_pad;                // PAD / IDENTITY: padded dimension
+  int64_t n, lda;           // PAD: the caller's n and leading dimension
+  const void* src;          // PAD source
+  void* dst;
+  size_t bytes;             // ZERO: bytes to clear (a multiple of 4)
+};
+constexpr int kMaxFills = 4;
+hipError_t launch_fills(const Fill* fills, int count, hipStream_t s);
+
 }  // namespace ns

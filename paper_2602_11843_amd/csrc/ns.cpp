@@ -307,17 +307,19 @@ struct Out {
   double id;
 };
 
-// A recorded device operation of a schedule.
+// A recorded device operation of a call.
 struct Op {
-  enum Kind { GEMM, IDENTITY, AMAX, PANELS } kind;
+  enum Kind { GEMM, IDENTITY, AMAX, PANELS, ZERO, PAD, UNPAD } kind;
   Engine e;
   GemmParams p;      // GEMM
   bool panels;       // GEMM: X / Y are 16-bit panels
-  void* ptr;         // IDENTITY / AMAX target, PANELS source
-  int f64;
+  void* ptr;         // IDENTITY / AMAX / ZERO target, PANELS / PAD / UNPAD source
+  int f64;           // element type of the target (PAD / UNPAD: of the destination)
   unsigned* amax;
-  void* dst;         // PANELS destination
+  void* dst;         // PANELS / PAD / UNPAD destination
   int transpose;     // PANELS: 1 for a Y operand
+  int src_f64;       // PAD / UNPAD: element type of the source
+  int64_t n, ld;     // PAD / UNPAD: the caller's n and leading dimension; ZERO: bytes in n
 };
 
 struct Ctx {
@@ -358,6 +360,40 @@ struct Ctx {
     op.kind = Op::IDENTITY;
     op.ptr = b.p;
     op.f64 = b.f64;
+    ops.push_back(op);
+  }
+
+  void zero(void* p, size_t bytes) {
+    Op op{};
+    op.kind = Op::ZERO;
+    op.ptr = p;
+    op.n = (int64_t)bytes;
+    ops.push_back(op);
+  }
+
+  // padded working copy dst <- the caller's n x n matrix src (leading dim ld)
+  void pad(const void* src, int src_f64, int64_t ld, const Buf& dst) {
+    Op op{};
+    op.kind = Op::PAD;
+    op.ptr = const_cast<void*>(src);
+    op.src_f64 = src_f64;
+    op.dst = dst.p;
+    op.f64 = dst.f64;
+    op.n = n;
+    op.ld = ld;
+    ops.push_back(op);
+  }
+
+  // the caller's n x n result dst (leading dim ld) <- top-left block of src
+  void unpad(const Buf& src, void* dst, int dst_f64, int64_t ld) {
+    Op op{};
+    op.kind = Op::UNPAD;
+    op.ptr = src.p;
+    op.src_f64 = src.f64;
+    op.dst = dst;
+    op.f64 = dst_f64;
+    op.n = n;
+    op.ld = ld;
     ops.push_back(op);
   }
 
@@ -482,9 +518,35 @@ struct Ctx {
       NS_HIP(hipEventRecord(h->params_free, s));
     }
     gi = 0;
-    for (const Op& op : ops) {
-      if (op.kind == Op::IDENTITY) {
-        NS_HIP(launch_set_identity(op.ptr, op.f64, np, s));
+    for (size_t oi = 0; oi < ops.size(); ++oi) {
+      const Op& op = ops[oi];
+      if (op.kind == Op::ZERO || op.kind == Op::PAD || op.kind == Op::IDENTITY) {
+        // a run of consecutive fills (the call's prologue: scalar reset,
+        // copies-in, identities) goes out as one launch; they write distinct
+        // buffers and read only the caller's A
+        Fill f[kMaxFills];
+        int nf = 0;
+        for (; oi < ops.size() && nf < kMaxFills; ++oi) {
+          const Op& x = ops[oi];
+          if (x.kind != Op::ZERO && x.kind != Op::PAD && x.kind != Op::IDENTITY) break;
+          Fill& y = f[nf++];
+          y = Fill{};
+          y.kind = x.kind == Op::ZERO ? FILL_ZERO : x.kind == Op::PAD ? FILL_PAD : FILL_IDENTITY;
+          y.src_f64 = x.src_f64;
+          y.dst_f64 = x.f64;
+          y.n_pad = np;
+          y.n = x.n;
+          y.lda = x.ld;
+          y.src = x.ptr;
+          y.dst = x.kind == Op::PAD ? x.dst : x.ptr;
+          y.bytes = x.kind == Op::ZERO ? (size_t)x.n : 0;
+        }
+        --oi;   // the loop's own increment moves past the run
+        NS_HIP(launch_fills(f, nf, s));
+        continue;
+      }
+      if (op.kind == Op::UNPAD) {
+        NS_HIP(launch_unpad_copy(op.ptr, op.src_f64, np, op.dst, op.f64, op.n, op.ld, s));
         continue;
       }
       if (op.kind == Op::AMAX) {
@@ -828,23 +890,22 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   c.mixed = is_mixed(dtype);
   c.scal = static_cast<Scalars*>(h->ws);
   c.arena = static_cast<char*>(h->ws) + kScalarBytes;
-  NS_HIP(launch_zero_words(c.scal, sizeof(Scalars), s));
+  c.zero(c.scal, sizeof(Scalars));
 
   const int in64 = (dtype != NS_F32);
   const int W64 = (c.eng == ENG_F64);
   Buf Aw = c.take(W64);
-  NS_HIP(launch_pad_copy(A, in64, n, lda, Aw.p, W64, c.np, s));
+  c.pad(A, in64, lda, Aw);
   Buf A64;
   if (c.mixed && is_residual(method)) {
     A64 = c.take(1);
-    NS_HIP(launch_pad_copy(A, 1, n, lda, A64.p, 1, c.np, s));
+    c.pad(A, 1, lda, A64);
   }
   if (c.eng == ENG_F16S) c.amax(Aw);
   Result res;
   if ((st = run_schedule(c, method, k, levels, Aw, c.mixed ? &A64 : nullptr, &res))) return st;
+  c.unpad(res.S, out, in64, ldo);
   if ((st = c.execute())) return st;
-  const int out64 = in64;
-  NS_HIP(launch_unpad_copy(res.S.p, res.S.f64, c.np, out, out64, n, ldo, s));
   NS_HIP(hipEventRecord(h->call_done, s));
 
   if (rep) {

@@ -53,6 +53,56 @@ __global__ void amax_kernel(const float* __restrict__ x, size_t count, unsigned*
   if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
 }
 
+struct FillSet {
+  Fill f[kMaxFills];
+  int first_block[kMaxFills + 1];   // fill i owns blocks [first_block[i], first_block[i + 1])
+  int count;
+};
+
+template <class S, class D>
+__device__ void pad_range(const Fill& f, size_t i0, size_t step) {
+  const S* __restrict__ src = static_cast<const S*>(f.src);
+  D* __restrict__ dst = static_cast<D*>(f.dst);
+  const size_t total = (size_t)f.n_pad * f.n_pad;
+  for (size_t i = i0; i < total; i += step) {
+    const int64_t r = (int64_t)(i / f.n_pad), c = (int64_t)(i % f.n_pad);
+    dst[i] = (r < f.n && c < f.n) ? (D)src[r * f.lda + c] : (D)0;
+  }
+}
+
+template <class D>
+__device__ void identity_range(const Fill& f, size_t i0, size_t step) {
+  D* __restrict__ dst = static_cast<D*>(f.dst);
+  const size_t total = (size_t)f.n_pad * f.n_pad;
+  for (size_t i = i0; i < total; i += step) dst[i] = (i / f.n_pad == i % f.n_pad) ? (D)1 : (D)0;
+}
+
+__global__ void fills_kernel(const FillSet set) {
+  int k = 0;
+  while (k + 1 < set.count && (int)blockIdx.x >= set.first_block[k + 1]) ++k;
+  const Fill& f = set.f[k];
+  const int nb = set.first_block[k + 1] - set.first_block[k];
+  const size_t i0 = (size_t)(blockIdx.x - set.first_block[k]) * blockDim.x + threadIdx.x;
+  const size_t step = (size_t)nb * blockDim.x;
+  switch (f.kind) {
+    case FILL_ZERO: {
+      unsigned* p = static_cast<unsigned*>(f.dst);
+      for (size_t i = i0; i < f.bytes / 4; i += step) p[i] = 0u;
+      break;
+    }
+    case FILL_PAD:
+      if (f.src_f64 && f.dst_f64) pad_range<double, double>(f, i0, step);
+      else if (f.src_f64) pad_range<double, float>(f, i0, step);
+      else if (f.dst_f64) pad_range<float, double>(f, i0, step);
+      else pad_range<float, float>(f, i0, step);
+      break;
+    default:
+      if (f.dst_f64) identity_range<double>(f, i0, step);
+      else identity_range<float>(f, i0, step);
+      break;
+  }
+}
+
 inline int grid_for(size_t total) {
   size_t g = (total + 255) / 256;
   if (g > 4096) g = 4096;
@@ -111,6 +161,24 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   if (words == 0) return hipSuccess;
   hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(words)), dim3(256), 0, s, (unsigned*)p, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_fills(const Fill* fills, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxFills) return hipErrorInvalidValue;
+  FillSet set{};
+  set.count = count;
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    set.f[i] = fills[i];
+    set.first_block[i] = blocks;
+    const size_t elems = fills[i].kind == FILL_ZERO ? fills[i].bytes / 4
+                                                    : (size_t)fills[i].n_pad * fills[i].n_pad;
+    blocks += grid_for(elems);
+  }
+  set.first_block[count] = blocks;
+  hipLaunchKernelGGL(fills_kernel, dim3(blocks), dim3(256), 0, s, set);
   return hipGetLastError();
 }
 
