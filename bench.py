@@ -145,13 +145,13 @@ def cpu_oracle_sample(fn, label, flops, min_seconds=10.0, max_runs=50):
                  "sample": f"{label}: {runs} run(s), {sec:.2f} s each, {total:.1f} s in all ({cpu_model()})"}
 
 
-def measured_traffic(summary="pmc_product_f64_large_symmetric.md"):
+def measured_traffic(summary="pmc_product_f64_large_symmetric.md", root=None):
     """HBM-side bytes per launch of the FP64 product kernel from the committed
     rocprofv3 counter summary, or None once the kernel source or the product
     schedule (which sets each launch's epilogue) has changed since the
     counters were taken (the summary records a source hash)."""
     import hashlib
-    root = os.path.dirname(os.path.abspath(__file__))
+    root = root or os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", summary)
     try:
         vals = {}
