@@ -52,8 +52,11 @@ hipError_t launch_low(const GemmParams& host, const GemmParams* dev, hipStream_t
 // here a wave waits about once per batch.  The four partial tiles are summed
 // in LDS in wave order before the shared epilogue.  (Above n = 256 the 16 x 16
 // tiles re-read X and Y too often: 1.7x slower than 32 x 32 at n = 384.)
-// Operand lanes (see PolF64): A_b[i][k] at i = l & 3, k = 4 b + (l >> 4);
-// B_b[k][j] at j = l & 3; block b = (l >> 2) & 3.
+// v_mfma_f64_4x4x4f64 lanes (decoded on the device): block b = (l >> 2) & 3
+// holds A_b[i][k] at i = l & 3, k = l >> 4 and B_b[k][j] at j = l & 3; its
+// result D_b[i][j] sits at i = l >> 4, j = l & 3.  Here the four blocks take
+// four disjoint k-slices (k = 4 b + (l >> 4) within a 16-wide chunk) of one
+// 4x4 output fragment, and their partial sums are added across lanes.
 // ---------------------------------------------------------------------------
 constexpr int SK_TILE = 16, SK_WAVES = 4, SK_CB = 4;
 constexpr int kSplitKMin = 160, kSplitKMax = 256;
