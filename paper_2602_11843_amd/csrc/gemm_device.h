@@ -570,13 +570,15 @@ struct DmaPlan {
       const int ins = wave + i * D::NW;                // this instruction's 1 KB run of the X tile
       // LDS chunk v % ROW_VEC of row r holds global chunk (v % ROW_VEC) ^ a_swz(r)
       const int v = ins * 64 + lane, r = v / ROW_VEC, c = ((v % ROW_VEC) ^ P::a_swz(r)) * EPV;
-      a_off[i] = (uint32_t)((row0 + r) * ld + c);
+      // element offsets stay below n^2 <= 2^32 (n <= 65536): unsigned 32-bit
+      // arithmetic is exact, where signed int would overflow past n = 46340
+      a_off[i] = (uint32_t)(row0 + r) * (uint32_t)ld + (uint32_t)c;
       a_lds[i] = ins * (1024 / (int)sizeof(T));
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int r = wave + i * D::NW;                  // one Y-tile row per instruction
-      b_off[i] = (uint32_t)(r * ld + col0 + (lane ^ P::b_swz(r)) * EPV);
+      b_off[i] = (uint32_t)r * (uint32_t)ld + (uint32_t)(col0 + (lane ^ P::b_swz(r)) * EPV);
       b_lds[i] = r * P::BPITCH;
     }
   }

@@ -198,6 +198,41 @@ def test_repeat_calls_are_deterministic(ns):
 
 # --- large sizes: sampled outputs against the definition --------------------
 
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_element_offsets_past_2_31(ns, dtype):
+    """n = 46400 (padded to 46592 or 46464): element offsets past 2^31 in every product
+    kernel's loads and stores.  Binary splitting at k = 2 on a diagonal A is
+    S = I + A exactly (each product entry has one nonzero term), so entries
+    sampled over the whole matrix, the last rows and columns included, are
+    compared bit for bit."""
+    n = 46400
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    g = torch.Generator(device="cuda").manual_seed(4640)
+    d = (torch.rand(n, device="cuda", generator=g, dtype=torch.float64) - 0.5).to(tdt)
+    A = torch.zeros(n, n, device="cuda", dtype=tdt)
+    A.diagonal().copy_(d)
+    h = ns.Handle(0)
+    say(f"[gpu] offsets past 2^31: binary k=2 {dtype} n={n}")
+    out, rep = ns.ns_eval_ex(A, 2, "binary", dtype, handle=h, report=True)
+    torch.cuda.synchronize()
+    del A
+    rng = np.random.default_rng(46400)
+    rows = np.concatenate([rng.integers(0, n, 200), np.arange(n - 40, n)])
+    cols = np.concatenate([rng.integers(0, n, 200), np.arange(n - 40, n)])
+    ri, ci = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    got_diag = out[ri, ri].cpu()
+    want_diag = (1 + d[ri]).cpu()
+    assert torch.equal(got_diag, want_diag)
+    off = rows != cols
+    got_off = out[ri[torch.from_numpy(off).cuda()], ci[torch.from_numpy(off).cuda()]].cpu()
+    assert torch.count_nonzero(got_off) == 0
+    assert rep["n_internal"] == (46592 if dtype == "f32" else 46464) and not rep["nonfinite"]
+    del out
+    h.close()
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("method", ["binary", "radix9"])
 def test_large_symmetric_sampled_columns(ns, method, dtype):
