@@ -187,6 +187,20 @@ def test_argument_errors(ns):
     with pytest.raises(ns.NSError) as e:
         ns.ns_eval_ex(A, 9, "naive", "split_bf16")
     assert e.value.status == -2
+    empty = torch.zeros((0, 0), dtype=torch.float64, device="cuda")
+    with pytest.raises(ns.NSError) as e:
+        ns.ns_eval_ex(empty, 9, "radix9", "f64", out=torch.zeros((0, 0), dtype=torch.float64,
+                                                                  device="cuda"))
+    assert e.value.status == -1
+    # n above the supported range is refused before any memory is touched: both
+    # matrices are views of one short row (row stride 0), never read
+    n = 65537
+    row = torch.zeros(n, dtype=torch.float64, device="cuda")
+    other = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(ns.NSError) as e:
+        ns.ns_eval_ex(row.as_strided((n, n), (0, 1)), 9, "radix9", "f64",
+                      out=other.as_strided((n, n), (0, 1)))
+    assert e.value.status == -5
 
 
 def test_repeat_calls_are_deterministic(ns):
