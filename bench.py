@@ -23,6 +23,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -375,7 +376,8 @@ def bench_jacobi_batch(args, torch, ns):
     k = 81
     flops = float(sum(10 * 2.0 * int(m) ** 3 for m in w.ns))
     h = ns.Handle(0)
-    os.environ.setdefault("NS_TUNE_CACHE", os.path.join("gpurun_out", "ns_tune.jsonl"))
+    # the autotuner's pick is also written to this JSON-lines file
+    os.environ.setdefault("NS_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "ns_tune.jsonl"))
     os.makedirs(os.path.dirname(os.environ["NS_TUNE_CACHE"]) or ".", exist_ok=True)
     log("[bench] autotuning the batched kernel")
     timed = ns.ns_autotune_batched(A, offd, nd, nh, k, out, handle=h)
