@@ -176,7 +176,9 @@ int ns_eval_ex(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k,
    Supported: method NS_RADIX9 or NS_BINARY or NS_NAIVE, dtype NS_F32 (float
    buffers), 1 <= n_i <= 256.  The graph cache is keyed on the
    buffers, n histogram, k, method and dtype: a call with new pointers captures
-   a new graph.  rep (nullable) aggregates: level_norm holds the sum over
+   a new graph.  The handle keeps at most 16 graphs (the oldest is dropped
+   after a device synchronisation), and drops them all when a call or the
+   autotuner needs a larger workspace.  rep (nullable) aggregates: level_norm holds the sum over
    matrices of squared norms' square root per level, nonfinite is the OR. */
 int ns_eval_batched(ns_handle* h, const void* A_packed, const int64_t* off_dev,
                     const int32_t* n_dev, const int32_t* n_host, int32_t batch,

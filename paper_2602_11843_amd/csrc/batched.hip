@@ -309,6 +309,19 @@ struct GraphEntry {
   int grid = 0;
 };
 
+// Graphs cached per handle; beyond this many the oldest is dropped, so that
+// calls on ever new buffers do not accumulate graphs and order arrays.
+constexpr size_t kMaxGraphs = 16;
+
+// Release one cached graph.  Its kernel arguments hold the workspace address
+// and its order array, so the caller has synchronised the device first.
+void drop_graph(GraphEntry& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  if (g.order) (void)hipFree(g.order);
+  g = GraphEntry{};
+}
+
 struct State {
   int cus = 0;
   float* work = nullptr;
@@ -350,6 +363,10 @@ int state_of(ns_handle* h, State** out) {
 int ensure_slots(State* st, size_t slots) {
   if (st->work_slots >= slots) return NS_OK;
   B_HIP(hipDeviceSynchronize());
+  // every cached graph has the old workspace address in its kernel
+  // arguments: drop them all, and the next call on each key captures again
+  for (auto& g : st->graphs) drop_graph(g);
+  st->graphs.clear();
   if (st->work) B_HIP(hipFree(st->work));
   st->work = nullptr;
   st->work_slots = 0;
@@ -480,6 +497,11 @@ int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, con
   for (auto& g : st->graphs)
     if (g.key == key && g.cfg.big == cfg.big && g.cfg.per_cu == cfg.per_cu) ge = &g;
   if (!ge) {
+    if (st->graphs.size() >= kMaxGraphs) {
+      B_HIP(hipDeviceSynchronize());             // the oldest graph may still be in flight
+      drop_graph(st->graphs.front());
+      st->graphs.erase(st->graphs.begin());
+    }
     GraphEntry g;
     g.key = key;
     g.cfg = cfg;
@@ -585,11 +607,7 @@ int batched_autotune(ns_handle* h, const void* A_packed, const int64_t* off_dev,
 void batched_release(ns_handle* h) {
   State* st = static_cast<State*>(handle_batched_state(h));
   if (!st) return;
-  for (auto& g : st->graphs) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
-    if (g.order) (void)hipFree(g.order);
-  }
+  for (auto& g : st->graphs) drop_graph(g);
   if (st->work) (void)hipFree(st->work);
   if (st->counters) (void)hipFree(st->counters);
   if (st->sumsq) (void)hipFree(st->sumsq);

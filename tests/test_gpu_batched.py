@@ -147,6 +147,49 @@ def test_autotune_then_evaluate(ns, tmp_path, monkeypatch):
     h.close()
 
 
+def test_graph_cache_after_workspace_growth_and_eviction(ns, tmp_path, monkeypatch):
+    """One handle evaluates a small batch, then makes calls that grow its
+    workspace (the autotuner on a larger batch, then a larger batch still),
+    then uses more distinct buffer sets than its graph cache holds.  Every
+    repeat of the small batch must equal its first result: graphs captured
+    against an older workspace are captured again, never replayed."""
+    monkeypatch.setenv("NS_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    h = ns.Handle(0)
+    small = device_batch(mixed_batch(7)[:3])
+    large = device_batch(mixed_batch(8))
+    larger = device_batch(mixed_batch(9) + mixed_batch(10))
+
+    def run(b, out):
+        A, offd, nd, nh = b[:4]
+        return ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", out_packed=out, handle=h)
+
+    out_s = torch.empty_like(small[0])
+    first = run(small, out_s).clone()
+    torch.cuda.synchronize()
+
+    def check(tag):
+        out_s.zero_()
+        run(small, out_s)
+        torch.cuda.synchronize()
+        assert torch.equal(out_s, first), tag
+
+    say(f"[gpu] graph cache: autotuner on batch={len(large[4])}")
+    A, offd, nd, nh = large[:4]
+    ns.ns_autotune_batched(A, offd, nd, nh, 81, torch.empty_like(A), handle=h)
+    check("after autotuning a larger batch")
+    say(f"[gpu] graph cache: batch={len(larger[4])}")
+    run(larger, torch.empty_like(larger[0]))
+    check("after a larger batch")
+    say("[gpu] graph cache: 20 more buffer sets")
+    keep = []                      # distinct buffers, so that each call has its own graph
+    for i in range(20):
+        b = device_batch(mixed_batch(11 + i)[:2])
+        keep.append(b)
+        run(b, torch.empty_like(b[0]))
+    check("after eviction")
+    h.close()
+
+
 def hist_key(ns_):
     """The batched path's key for a batch's n histogram (ascending n)."""
     vals, counts = np.unique(ns_, return_counts=True)
