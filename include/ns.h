@@ -156,7 +156,8 @@ int ns_workspace_bytes(int64_t n, int method, int dtype, size_t* bytes);
 
 /* S_k(A) with a per-device default handle on the null stream; lda = ldo = n.
    Element type of A and out: double for NS_F64 and the mixed forms,
-   float for NS_F32. */
+   float for NS_F32.  Calls from several host threads are serialised on the
+   host (they share the default handle) and run in order on the null stream. */
 int ns_eval(const void* A, int64_t n, int64_t k, int method, int dtype, void* out);
 
 /* Full form.  lda, ldo: leading dimensions (>= n).  stream may be 0.

@@ -10,6 +10,7 @@ paper_2602_11843_amd.build``); there is no CPU fallback.
 
 import ctypes
 import os
+import threading
 from typing import Optional
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -160,17 +161,21 @@ def ns_status_string(status: int) -> str:
 # ---------------------------------------------------------------------------
 
 class Handle:
-    """Owns an ns_handle (workspace, timing, batched graphs) on one device."""
+    """Owns an ns_handle (workspace, timing, batched graphs) on one device.
+    Calls on one handle must not overlap, and ctypes releases the GIL during
+    a call, so every call through the handle holds its lock."""
 
     def __init__(self, device: int = 0):
         self.ptr = _P()
+        self.lock = threading.Lock()
         _check(lib.ns_create(ctypes.byref(self.ptr), int(device)), "ns_create")
         self.device = device
 
     def close(self):
         if self.ptr:
-            lib.ns_destroy(self.ptr)
-            self.ptr = _P()
+            with self.lock:
+                lib.ns_destroy(self.ptr)
+                self.ptr = _P()
 
     def __del__(self):
         try:
@@ -179,25 +184,29 @@ class Handle:
             pass
 
     def ns_set_product_timing(self, enable: bool):
-        _check(lib.ns_set_product_timing(self.ptr, int(bool(enable))), "ns_set_product_timing")
+        with self.lock:
+            _check(lib.ns_set_product_timing(self.ptr, int(bool(enable))), "ns_set_product_timing")
 
     def ns_product_timing(self, reset: bool = True):
         """(launches, summed kernel ms, summed algorithmic flops) since the last reset."""
         cnt, ms, fl = _I32(), _D(), _D()
-        _check(lib.ns_product_timing(self.ptr, ctypes.byref(cnt), ctypes.byref(ms),
-                                     ctypes.byref(fl), int(bool(reset))), "ns_product_timing")
+        with self.lock:
+            _check(lib.ns_product_timing(self.ptr, ctypes.byref(cnt), ctypes.byref(ms),
+                                         ctypes.byref(fl), int(bool(reset))), "ns_product_timing")
         return cnt.value, ms.value, fl.value
 
 
 _handles = {}
+_handles_lock = threading.Lock()
 
 
 def default_handle(device: Optional[int] = None) -> Handle:
     import torch
     dev = torch.cuda.current_device() if device is None else device
-    if dev not in _handles:
-        _handles[dev] = Handle(dev)
-    return _handles[dev]
+    with _handles_lock:
+        if dev not in _handles:
+            _handles[dev] = Handle(dev)
+        return _handles[dev]
 
 
 def _stream_ptr(stream):
@@ -231,9 +240,10 @@ def ns_eval_ex(A, k: int, method="radix9", dtype="f64", out=None, handle: Option
         out = torch.empty((n, n), dtype=A.dtype, device=A.device)
     h = handle or default_handle(A.device.index)
     rep = Report() if report else None
-    _check(lib.ns_eval_ex(h.ptr, _P(A.data_ptr()), n, A.stride(0), int(k), int(m), int(d),
-                          _P(out.data_ptr()), out.stride(0), _stream_ptr(stream),
-                          ctypes.byref(rep) if rep is not None else None), "ns_eval_ex")
+    with h.lock:
+        _check(lib.ns_eval_ex(h.ptr, _P(A.data_ptr()), n, A.stride(0), int(k), int(m), int(d),
+                              _P(out.data_ptr()), out.stride(0), _stream_ptr(stream),
+                              ctypes.byref(rep) if rep is not None else None), "ns_eval_ex")
     return (out, rep.as_dict()) if report else out
 
 
@@ -258,12 +268,13 @@ def ns_eval_batched(A_packed, offsets_dev, n_dev, n_host, k: int, method="radix9
         out_packed = torch.empty_like(A_packed)
     n_host = n_host.to(torch.int32).contiguous().cpu()
     rep = Report() if report else None
-    _check(lib.ns_eval_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
-                               _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host), int(k),
-                               int(METHODS.get(method, method)), int(DTYPES.get(dtype, dtype)),
-                               _P(out_packed.data_ptr()), _stream_ptr(stream),
-                               ctypes.byref(rep) if rep is not None else None),
-           "ns_eval_batched")
+    with h.lock:
+        _check(lib.ns_eval_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
+                                   _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host), int(k),
+                                   int(METHODS.get(method, method)), int(DTYPES.get(dtype, dtype)),
+                                   _P(out_packed.data_ptr()), _stream_ptr(stream),
+                                   ctypes.byref(rep) if rep is not None else None),
+               "ns_eval_batched")
     return (out_packed, rep.as_dict()) if report else out_packed
 
 
@@ -276,11 +287,12 @@ def ns_eval_batched_loop(A_packed, offsets_host, n_host, k: int, method="radix9"
         out_packed = torch.empty_like(A_packed)
     offs = offsets_host.to(torch.int64).contiguous().cpu()
     n_host = n_host.to(torch.int32).contiguous().cpu()
-    _check(lib.ns_eval_batched_loop(h.ptr, _P(A_packed.data_ptr()), _P(offs.data_ptr()),
-                                    _P(n_host.data_ptr()), len(n_host), int(k),
-                                    int(METHODS.get(method, method)),
-                                    int(DTYPES.get(dtype, dtype)), _P(out_packed.data_ptr()),
-                                    _stream_ptr(stream)), "ns_eval_batched_loop")
+    with h.lock:
+        _check(lib.ns_eval_batched_loop(h.ptr, _P(A_packed.data_ptr()), _P(offs.data_ptr()),
+                                        _P(n_host.data_ptr()), len(n_host), int(k),
+                                        int(METHODS.get(method, method)),
+                                        int(DTYPES.get(dtype, dtype)), _P(out_packed.data_ptr()),
+                                        _stream_ptr(stream)), "ns_eval_batched_loop")
     return out_packed
 
 
@@ -290,8 +302,9 @@ def ns_autotune_batched(A_packed, offsets_dev, n_dev, n_host, k: int, out_packed
     h = handle or default_handle(A_packed.device.index)
     n_host = n_host.to(torch.int32).contiguous().cpu()
     cnt = _I32()
-    _check(lib.ns_autotune_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
-                                   _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host),
-                                   int(k), _P(out_packed.data_ptr()), _stream_ptr(stream),
-                                   ctypes.byref(cnt)), "ns_autotune_batched")
+    with h.lock:
+        _check(lib.ns_autotune_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
+                                       _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host),
+                                       int(k), _P(out_packed.data_ptr()), _stream_ptr(stream),
+                                       ctypes.byref(cnt)), "ns_autotune_batched")
     return cnt.value

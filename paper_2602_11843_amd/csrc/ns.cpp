@@ -1006,16 +1006,14 @@ int ns_eval(const void* A, int64_t n, int64_t k, int method, int dtype, void* ou
   int dev = 0;
   NS_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(NS_ERR_ARG, "device index %d", dev);
-  ns_handle* h;
-  {
-    std::lock_guard<std::mutex> lk(ns::g_default_mu);
-    if (!ns::g_default[dev]) {
-      const int st = ns_create(&ns::g_default[dev], dev);
-      if (st) return st;
-    }
-    h = ns::g_default[dev];
+  // every host thread shares the default handle, so the whole call (the
+  // host-side recording and enqueueing) runs under the lock
+  std::lock_guard<std::mutex> lk(ns::g_default_mu);
+  if (!ns::g_default[dev]) {
+    const int st = ns_create(&ns::g_default[dev], dev);
+    if (st) return st;
   }
-  return ns_eval_ex(h, A, n, n, k, method, dtype, out, n, nullptr, nullptr);
+  return ns_eval_ex(ns::g_default[dev], A, n, n, k, method, dtype, out, n, nullptr, nullptr);
 }
 
 int ns_eval_batched(ns_handle* h, const void* A_packed, const int64_t* off_dev,

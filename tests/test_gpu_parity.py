@@ -210,6 +210,38 @@ def test_repeat_calls_are_deterministic(ns):
     assert np.array_equal(a, b)
 
 
+def test_threads_share_the_default_handles(ns):
+    """Host threads calling the short form (the library's default handle)
+    and the full form without a handle (the binding's default handle) at the
+    same time: every result equals the one computed alone."""
+    import threading
+    sizes = (96, 130, 200, 300)
+    A = [dev(workloads.symmetric(n, 0.8, 20 + i).A, "f64") for i, n in enumerate(sizes)]
+    ref_short = [ns.ns_eval(a, 81, "radix9", "f64") for a in A]
+    ref_full = [ns.ns_eval_ex(a, 81, "radix9", "f64") for a in A]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(i):
+        try:
+            for r in range(5):
+                s = ns.ns_eval(A[i], 81, "radix9", "f64")
+                f = ns.ns_eval_ex(A[i], 81, "radix9", "f64")
+                torch.cuda.synchronize()
+                if not (torch.equal(s, ref_short[i]) and torch.equal(f, ref_full[i])):
+                    errors.append((sizes[i], r))
+        except Exception as e:          # reported below, in the main thread
+            errors.append((sizes[i], repr(e)))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(A))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+
+
 # --- large sizes: sampled outputs against the definition --------------------
 
 @pytest.mark.slow
