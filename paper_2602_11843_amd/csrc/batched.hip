@@ -478,7 +478,8 @@ int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, con
   if (rc) return rc;
   int32_t levels;
   if ((rc = levels_for(k, method, &levels))) return rc;
-  B_HIP(hipSetDevice(handle_device(h)));
+  const DeviceGuard dg(handle_device(h));
+  B_HIP(dg.err);
   State* st;
   if ((rc = state_of(h, &st))) return rc;
   load_tuned(st);
@@ -556,7 +557,8 @@ int batched_autotune(ns_handle* h, const void* A_packed, const int64_t* off_dev,
   if (rc) return rc;
   int32_t levels;
   if ((rc = levels_for(k, NS_RADIX9, &levels))) return rc;
-  B_HIP(hipSetDevice(handle_device(h)));
+  const DeviceGuard dg(handle_device(h));
+  B_HIP(dg.err);
   State* st;
   if ((rc = state_of(h, &st))) return rc;
   load_tuned(st);

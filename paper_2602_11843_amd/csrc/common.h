@@ -104,4 +104,26 @@ struct Fill {
 constexpr int kMaxFills = 4;
 hipError_t launch_fills(const Fill* fills, int count, hipStream_t s);
 
+
+// Makes a handle's device current for the guard's lifetime and restores the
+// caller's device afterwards: an entry point never changes the calling
+// thread's current device.  err holds the first failing runtime call.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int device) {
+    int cur = -1;
+    err = hipGetDevice(&cur);
+    if (err == hipSuccess && cur != device) {
+      err = hipSetDevice(device);
+      if (err == hipSuccess) prev = cur;
+    }
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
+
 }  // namespace ns

@@ -876,7 +876,8 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   int64_t k_eff;
   int32_t levels, gemms_formula;
   if ((st = plan(k, method, &k_eff, &levels, &gemms_formula))) return st;
-  NS_HIP(hipSetDevice(h->device));
+  const DeviceGuard dg(h->device);
+  NS_HIP(dg.err);
   if ((st = ensure_workspace(h, workspace_bytes(n, method, dtype)))) return st;
   if (!h->call_done) NS_HIP(hipEventCreateWithFlags(&h->call_done, hipEventDisableTiming));
   else NS_HIP(hipStreamWaitEvent(s, h->call_done, 0));
@@ -960,15 +961,17 @@ int ns_create(ns_handle** h, int device) {
 
 int ns_destroy(ns_handle* h) {
   if (!h) return NS_OK;
-  (void)hipSetDevice(h->device);
-  (void)hipDeviceSynchronize();
-  ns::batched_release(h);
-  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-  if (h->params_free) (void)hipEventDestroy(h->params_free);
-  if (h->call_done) (void)hipEventDestroy(h->call_done);
-  if (h->params_host) (void)hipHostFree(h->params_host);
-  if (h->params_dev) (void)hipFree(h->params_dev);
-  if (h->ws) (void)hipFree(h->ws);
+  {
+    const ns::DeviceGuard dg(h->device);
+    (void)hipDeviceSynchronize();
+    ns::batched_release(h);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->params_free) (void)hipEventDestroy(h->params_free);
+    if (h->call_done) (void)hipEventDestroy(h->call_done);
+    if (h->params_host) (void)hipHostFree(h->params_host);
+    if (h->params_dev) (void)hipFree(h->params_dev);
+    if (h->ws) (void)hipFree(h->ws);
+  }
   delete h;
   return NS_OK;
 }
