@@ -222,6 +222,53 @@ def io_dtype(dtype):
     return torch.float32 if DTYPES.get(dtype, dtype) == F32 else torch.float64
 
 
+# Argument checks of the binding: the library receives bare pointers, so a
+# tensor of the wrong element type or layout would be read as something else.
+# Leading dimensions, sizes and overlap are checked again by the library.
+
+def _cuda_tensor(name, T, dtype, device=None):
+    import torch
+    if not isinstance(T, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if T.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {T.dtype}")
+    if not T.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if device is not None and T.device != device:
+        raise ValueError(f"{name} must be on {device}, got {T.device}")
+
+
+def _square(name, T, dtype, n=None, device=None, contiguous=False):
+    _cuda_tensor(name, T, dtype, device)
+    if T.dim() != 2 or T.shape[0] != T.shape[1] or (n is not None and T.shape[0] != n):
+        raise ValueError(f"{name} must be a square matrix" + (f" of order {n}" if n is not None else ""))
+    if T.stride(1) != 1 or (contiguous and not T.is_contiguous()):
+        raise ValueError(f"{name} must be row-major" + (" and contiguous" if contiguous
+                                                          else " with unit column stride"))
+
+
+def _packed(A_packed, n_host, out_packed, offsets_dev=None, n_dev=None):
+    import torch
+    args = [("A_packed", A_packed, torch.float32), ("out_packed", out_packed, torch.float32),
+            ("offsets_dev", offsets_dev, torch.int64), ("n_dev", n_dev, torch.int32)]
+    args = [a for a in args if a[1] is not None]
+    for name, T, dt in args:                       # element types first, then placement
+        if not isinstance(T, torch.Tensor) or T.dtype != dt:
+            raise TypeError(f"{name} must be a {dt} tensor")
+    for name, T, dt in args:
+        _cuda_tensor(name, T, dt, A_packed.device)
+        if not T.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if out_packed.numel() != A_packed.numel():
+        raise ValueError("out_packed must have as many elements as A_packed")
+    batch = len(n_host)
+    for name, T in (("offsets_dev", offsets_dev), ("n_dev", n_dev)):
+        if T is not None and T.numel() < batch:
+            raise ValueError(f"{name} must have an entry per matrix")
+    if batch and int((n_host.to(torch.int64) ** 2).sum()) > A_packed.numel():
+        raise ValueError("A_packed holds fewer elements than the matrices need")
+
+
 def ns_eval_ex(A, k: int, method="radix9", dtype="f64", out=None, handle: Optional[Handle] = None,
          stream=None, report: bool = False):
     """S_k(A) for a square CUDA tensor A (row-major, any leading dimension
@@ -229,15 +276,11 @@ def ns_eval_ex(A, k: int, method="radix9", dtype="f64", out=None, handle: Option
     import torch
     m = METHODS.get(method, method)
     d = DTYPES.get(dtype, dtype)
-    if A.dim() != 2 or A.shape[0] != A.shape[1]:
-        raise ValueError("A must be a square matrix")
-    if A.dtype != io_dtype(d):
-        raise TypeError(f"A must be {io_dtype(d)} for this dtype")
-    if not A.is_cuda or A.stride(1) != 1:
-        raise ValueError("A must be a CUDA tensor with unit column stride")
+    _square("A", A, io_dtype(d))
     n = A.shape[0]
     if out is None:
         out = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    _square("out", out, A.dtype, n, A.device)
     h = handle or default_handle(A.device.index)
     rep = Report() if report else None
     with h.lock:
@@ -251,8 +294,10 @@ def ns_eval(A, k: int, method="radix9", dtype="f64", out=None):
     """The short form (per-device default handle, null stream, lda = n)."""
     import torch
     m, d = METHODS.get(method, method), DTYPES.get(dtype, dtype)
+    _square("A", A, io_dtype(d), contiguous=True)
     if out is None:
         out = torch.empty_like(A)
+    _square("out", out, A.dtype, A.shape[0], A.device, contiguous=True)
     _check(lib.ns_eval(_P(A.data_ptr()), A.shape[0], int(k), int(m), int(d), _P(out.data_ptr())),
            "ns_eval")
     return out
@@ -263,10 +308,11 @@ def ns_eval_batched(A_packed, offsets_dev, n_dev, n_host, k: int, method="radix9
                  report: bool = False):
     """Batched S_k over packed row-major float32 matrices (see ns.h)."""
     import torch
-    h = handle or default_handle(A_packed.device.index)
     if out_packed is None:
         out_packed = torch.empty_like(A_packed)
     n_host = n_host.to(torch.int32).contiguous().cpu()
+    _packed(A_packed, n_host, out_packed, offsets_dev, n_dev)
+    h = handle or default_handle(A_packed.device.index)
     rep = Report() if report else None
     with h.lock:
         _check(lib.ns_eval_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
@@ -282,11 +328,16 @@ def ns_eval_batched_loop(A_packed, offsets_host, n_host, k: int, method="radix9"
                       out_packed=None, handle: Optional[Handle] = None, stream=None):
     """The per-matrix launch loop over the same packed layout."""
     import torch
-    h = handle or default_handle(A_packed.device.index)
     if out_packed is None:
         out_packed = torch.empty_like(A_packed)
     offs = offsets_host.to(torch.int64).contiguous().cpu()
     n_host = n_host.to(torch.int32).contiguous().cpu()
+    _packed(A_packed, n_host, out_packed)
+    if len(offs) < len(n_host):
+        raise ValueError("offsets_host must have an entry per matrix")
+    if len(n_host) and int((offs[:len(n_host)] + n_host.to(torch.int64) ** 2).max()) > A_packed.numel():
+        raise ValueError("a matrix extends past the end of A_packed")
+    h = handle or default_handle(A_packed.device.index)
     with h.lock:
         _check(lib.ns_eval_batched_loop(h.ptr, _P(A_packed.data_ptr()), _P(offs.data_ptr()),
                                         _P(n_host.data_ptr()), len(n_host), int(k),
@@ -299,8 +350,9 @@ def ns_eval_batched_loop(A_packed, offsets_host, n_host, k: int, method="radix9"
 def ns_autotune_batched(A_packed, offsets_dev, n_dev, n_host, k: int, out_packed,
                      handle: Optional[Handle] = None, stream=None) -> int:
     import torch
-    h = handle or default_handle(A_packed.device.index)
     n_host = n_host.to(torch.int32).contiguous().cpu()
+    _packed(A_packed, n_host, out_packed, offsets_dev, n_dev)
+    h = handle or default_handle(A_packed.device.index)
     cnt = _I32()
     with h.lock:
         _check(lib.ns_autotune_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),

@@ -129,3 +129,26 @@ def test_mixed_plan_matches_oracle_for_every_k(ns):
     ks = list(range(1, 2001)) + [3375, 4095, 4097, 10 ** 6, 10 ** 9 + 7, 2 ** 40 + 5, 2 ** 62 + 1]
     for k in ks:
         assert ns.ns_plan(k, "mixed") == series.plan(k, "mixed"), k
+
+
+def test_binding_refuses_bad_tensors_before_the_library(ns):
+    """Wrong element types and host tensors are refused by the binding
+    itself, before any call into the library (none reaches the GPU)."""
+    import torch
+    A = torch.zeros((8, 8), dtype=torch.float64)
+    with pytest.raises(TypeError):
+        ns.ns_eval_ex(A.float(), 9, "radix9", "f64")            # FP64 I/O, FP32 tensor
+    with pytest.raises(TypeError):
+        ns.ns_eval_ex(A, 9, "radix9", "f32")                    # FP32 I/O, FP64 tensor
+    with pytest.raises(ValueError):
+        ns.ns_eval_ex(A, 9, "radix9", "f64")                    # host memory
+    with pytest.raises(TypeError):
+        ns.ns_eval(A.float(), 9, "radix9", "split_bf16")        # split forms take FP64
+    buf = torch.zeros(64, dtype=torch.float32)
+    n = torch.tensor([8], dtype=torch.int32)
+    with pytest.raises(TypeError):
+        ns.ns_eval_batched(buf, torch.zeros(1, dtype=torch.int32), n, n, 81)   # offsets are int64
+    with pytest.raises(TypeError):
+        ns.ns_eval_batched(buf.double(), torch.zeros(1, dtype=torch.int64), n, n, 81)
+    with pytest.raises(ValueError):
+        ns.ns_eval_batched_loop(buf, torch.zeros(1, dtype=torch.int64), n, 81)  # host memory

@@ -130,6 +130,24 @@ def test_batched_rejects_unsupported(ns):
     assert e.value.status == -2
 
 
+def test_binding_checks_packed_extents(ns):
+    """Packed buffers that cannot hold the matrices, or offsets of the wrong
+    type, are refused before any launch."""
+    mats = mixed_batch(12)[:4]
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    short = A[: A.numel() - 1]
+    with pytest.raises(ValueError):
+        ns.ns_eval_batched(short, offd, nd, nh, 81, "radix9", "f32")
+    with pytest.raises(TypeError):
+        ns.ns_eval_batched(A, offd.int(), nd, nh, 81, "radix9", "f32")
+    with pytest.raises(ValueError):
+        ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", out_packed=torch.empty_like(short))
+    bad = torch.from_numpy(offs).clone()
+    bad[-1] += 1                                   # last matrix now ends past the buffer
+    with pytest.raises(ValueError):
+        ns.ns_eval_batched_loop(A, bad, nh, 81, "radix9", "f32")
+
+
 def test_autotune_then_evaluate(ns, tmp_path, monkeypatch):
     monkeypatch.setenv("NS_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     mats = mixed_batch(5)
