@@ -296,6 +296,22 @@ def test_large_symmetric_sampled_columns(ns, method, dtype):
     assert err < TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [2100, 3000])
+def test_mid_sizes_sampled_columns(ns, n, dtype):
+    """Sizes between the small and the large tiles (FP32 keeps its small tile
+    up to 4096, FP64 switches at 2048), with a ragged tail: 16 sampled columns
+    against the spectral closed form."""
+    w = workloads.symmetric(n, 0.9, 40 + n)
+    got, rep = run(ns, w.A, 81, "radix9", dtype)
+    cols = np.sort(np.random.default_rng(1).choice(n, 16, replace=False))
+    cols[-1] = n - 1
+    ref = series.spectral_form(w.Q, w.lam, rep["k_eff"], cols=cols)
+    err = series.rel_fro(got[:, cols], ref)
+    say(f"   sampled rel err {err:.3e}  n_internal {rep['n_internal']}")
+    assert err < TOL[dtype]
+
+
 # --- exact S_k for any k (no round-up) ---------------------------------------
 
 MIXED_KS = [1, 2, 3, 4, 5, 7, 10, 16, 27, 100, 128, 1000, 3375, 4097]
