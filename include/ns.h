@@ -26,7 +26,12 @@
  *     (the paper evaluates pure powers k = m^t only, Sec. 6); k_eff is
  *     reported.  NS_NAIVE and NS_MIXED use k itself.  k = 1 gives I with no
  *     product.
- *   - One handle per host thread; calls that share a handle must not overlap.
+ *   - One handle per host thread; calls that share a handle must not overlap
+ *     (ns_eval, whose default handle every thread shares, serialises its
+ *     callers itself).  Consecutive calls on one handle may use different
+ *     streams: each call waits for the previous one on that handle.
+ *   - A call makes the handle's device current while it runs and restores the
+ *     calling thread's current device before returning.
  */
 #ifndef NS_H
 #define NS_H
