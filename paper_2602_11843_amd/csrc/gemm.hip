@@ -170,7 +170,7 @@ constexpr int kBigMinF32 = 4096;
 
 }  // namespace
 
-// below kPanelMin the low-precision engines convert on the way into LDS
+// below panel_min the low-precision engines convert on the way into LDS
 using BF3Small = PolLow<2, 2, 1, 1, true>;  // 64 x 64 tile
 using H16Small = PolLow<2, 2, 1, 1, false>;
 
@@ -179,7 +179,7 @@ int engine_tile(Engine e, int n) {
     case ENG_F64: return n >= kBigMin ? 128 : 32;
     case ENG_F32: return n >= kBigMinF32 ? 256 : 64;
     case ENG_BF16X3:
-    case ENG_F16S: return n >= kBigMin ? 256 : 64;
+    case ENG_F16S: return n >= panel_min(e) ? 256 : 64;
   }
   return 256;
 }
@@ -192,7 +192,7 @@ hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, 
       return launch<F64Small>(host, dev, s);
     case ENG_F32:
       return host.n >= kBigMinF32 ? launch<F32Big>(host, dev, s) : launch<F32Small>(host, dev, s);
-    // at n >= kPanelMin these engines run from panels (launch_gemm_panels)
+    // from panel_min these engines run from panels (launch_gemm_panels)
     case ENG_BF16X3: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<BF3Small>(host, dev, s);
     case ENG_F16S: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<H16Small>(host, dev, s);
   }

@@ -350,7 +350,7 @@ hipError_t launch_panel(const GemmParams& host, const GemmParams* dev, hipStream
 }  // namespace dev
 
 bool panel_path(Engine e, int n) {
-  return (e == ENG_BF16X3 || e == ENG_F16S) && n >= kPanelMin && n % 256 == 0;
+  return (e == ENG_BF16X3 || e == ENG_F16S) && n >= panel_min(e) && n % 256 == 0;
 }
 
 size_t panel_bytes(Engine e, int n) {

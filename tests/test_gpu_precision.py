@@ -116,13 +116,17 @@ def test_mixed_any_k_precision_forms(ns, dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["split_bf16", "f16_scaled"])
-def test_panel_path_with_padding(ns, dtype):
-    """n = 2100 pads to 2304: the 16-bit panel engines on a padded matrix
-    (the padding block must stay exactly zero through every product)."""
-    w = workloads.symmetric(2100, 0.9, 31)
+@pytest.mark.parametrize("n,n_internal", [(2100, 2176), (3100, 3328)])
+def test_low_precision_padding(ns, dtype, n, n_internal):
+    """Padded matrices on both 16-bit paths: n = 2100 converts in the k-loop
+    (64-wide tiles, padded to the FP64 tile, 2176); n = 3100 runs from panels
+    (256-wide tiles, 3328).  The padding block must stay exactly zero through
+    every product."""
+    w = workloads.symmetric(n, 0.9, 31)
     got, rep = run(ns, w.A, 81, "radix9", dtype)
-    assert rep["n_internal"] == 2304
-    ref = series.spectral_form(w.Q, w.lam, 81, cols=np.arange(0, 2100, 101))
-    err = series.rel_fro(got[:, 0:2100:101], ref)
+    assert rep["n_internal"] == n_internal
+    cols = np.arange(0, n, 101)
+    ref = series.spectral_form(w.Q, w.lam, 81, cols=cols)
+    err = series.rel_fro(got[:, cols], ref)
     say(f"   sampled rel err {err:.3e}")
     assert err < TOL[dtype]
