@@ -176,13 +176,16 @@ int ns_eval_ex(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k,
    cached HIP graph.
      A_packed, out_packed: device buffers; matrix i is row-major n_i x n_i,
        lda = n_i, starting at element offset off_dev[i] in both buffers.
-     off_dev (int64, device), n_dev (int32, device): per-matrix offset and n.
-     n_host (int32, host): the same n values, used to plan (bucketing, tile
-       choice, work order); they must equal n_dev.
+     off_dev (int64, device): per-matrix element offset.
+     n_host (int32, host): per-matrix n.  The library validates these, and
+       uploads its own copy with the work queue; the kernel reads n only from
+       there.
+     n_dev (int32, device): not read (the device copy of n of earlier
+       versions of this interface); may be null.
    Supported: method NS_RADIX9 or NS_BINARY or NS_NAIVE, dtype NS_F32 (float
    buffers), 1 <= n_i <= 256.  The graph cache is keyed on the
-   buffers, n histogram, k, method and dtype: a call with new pointers captures
-   a new graph.  The handle keeps at most 16 graphs (the oldest is dropped
+   buffers, the per-matrix n, k, method and dtype: a call with new pointers or
+   new n captures a new graph.  The handle keeps at most 16 graphs (the oldest is dropped
    after a device synchronisation), and drops them all when a call or the
    autotuner needs a larger workspace.  rep (nullable) aggregates: level_norm holds the sum over
    matrices of squared norms' square root per level, nonfinite is the OR. */

@@ -306,7 +306,9 @@ def ns_eval(A, k: int, method="radix9", dtype="f64", out=None):
 def ns_eval_batched(A_packed, offsets_dev, n_dev, n_host, k: int, method="radix9", dtype="f32",
                  out_packed=None, handle: Optional[Handle] = None, stream=None,
                  report: bool = False):
-    """Batched S_k over packed row-major float32 matrices (see ns.h)."""
+    """Batched S_k over packed row-major float32 matrices (see ns.h).  The
+    per-matrix n comes from n_host; n_dev is not read by the library and may
+    be None."""
     import torch
     if out_packed is None:
         out_packed = torch.empty_like(A_packed)
@@ -316,7 +318,8 @@ def ns_eval_batched(A_packed, offsets_dev, n_dev, n_host, k: int, method="radix9
     rep = Report() if report else None
     with h.lock:
         _check(lib.ns_eval_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
-                                   _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host), int(k),
+                                   _P(n_dev.data_ptr() if n_dev is not None else None),
+                                   _P(n_host.data_ptr()), len(n_host), int(k),
                                    int(METHODS.get(method, method)), int(DTYPES.get(dtype, dtype)),
                                    _P(out_packed.data_ptr()), _stream_ptr(stream),
                                    ctypes.byref(rep) if rep is not None else None),
@@ -356,7 +359,8 @@ def ns_autotune_batched(A_packed, offsets_dev, n_dev, n_host, k: int, out_packed
     cnt = _I32()
     with h.lock:
         _check(lib.ns_autotune_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
-                                       _P(n_dev.data_ptr()), _P(n_host.data_ptr()), len(n_host),
+                                       _P(n_dev.data_ptr() if n_dev is not None else None),
+                                       _P(n_host.data_ptr()), len(n_host),
                                        int(k), _P(out_packed.data_ptr()), _stream_ptr(stream),
                                        ctypes.byref(cnt)), "ns_autotune_batched")
     return cnt.value

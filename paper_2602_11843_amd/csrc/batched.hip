@@ -1,7 +1,7 @@
 // Batched S_k over thousands of small matrices of uneven n in ONE persistent
 // kernel launch (replayed from a cached HIP graph).
 //
-// Work distribution: a device queue of matrix indices in longest-first order
+// Work distribution: a device queue of (matrix index, n) pairs in longest-first order
 // (n descending, so the n = 256 matrices that carry most of the flops start
 // first and the small ones fill the tail).  Each workgroup pops a ticket,
 // evaluates that matrix's whole schedule itself, and pops again; when the
@@ -47,12 +47,19 @@ constexpr int kMaxBatchN = 256;
 constexpr int kSlotMats = 9;          // B, B', S, S', U, X1, P, Q, T
 constexpr int kThreads = 256;
 
+// One queue entry: matrix index and its n, taken from the caller's host array
+// (validated to lie in [1, 256] before upload) -- the kernel never reads the
+// caller's device copy of n.
+struct Item {
+  int32_t m;
+  int32_t n;
+};
+
 struct BatchArgs {
   const float* A;
   float* out;
   const int64_t* off;
-  const int32_t* nn;
-  const int32_t* order;
+  const Item* items;          // longest first
   int batch;
   int levels;
   int method;
@@ -117,8 +124,7 @@ __device__ __forceinline__ void ep_out(GemmParams& p, float* ptr, double a, doub
 // Forced inline: each tile's instance is called from several kernels, and a
 // call (measured) doubles the 128 x 128 kernel's private memory and its time.
 template <class P>
-__device__ __forceinline__ void one_matrix(const BatchArgs& a, int m, float* slot, float* smem) {
-  const int n = a.nn[m];
+__device__ __forceinline__ void one_matrix(const BatchArgs& a, int m, int n, float* slot, float* smem) {
   const int np = n <= 64 ? 64 : (n + 127) / 128 * 128;
   const size_t mat = (size_t)np * np;
   float* buf[kSlotMats];
@@ -233,10 +239,10 @@ __global__ __launch_bounds__(kThreads, MINB) void batched_kernel(const BatchArgs
     const unsigned t = s_ticket;
     __syncthreads();
     if (t >= (unsigned)a.batch) break;
-    const int m = a.order[t];
-    if (a.nn[m] <= 64) one_matrix<Small>(a, m, slot, smem);
-    else if (WIDE && a.nn[m] > 128) one_matrix<Wide>(a, m, slot, smem);
-    else one_matrix<Big>(a, m, slot, smem);
+    const Item it = a.items[t];
+    if (it.n <= 64) one_matrix<Small>(a, it.m, it.n, slot, smem);
+    else if (WIDE && it.n > 128) one_matrix<Wide>(a, it.m, it.n, slot, smem);
+    else one_matrix<Big>(a, it.m, it.n, slot, smem);
   }
   if (threadIdx.x == 0) {
     __threadfence();
@@ -302,23 +308,24 @@ int max_resident(const Config& c, int* out) {
 
 struct GraphEntry {
   std::string key;
+  std::vector<int32_t> n_host;    // the per-matrix n the items were built from
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  int32_t* order = nullptr;       // device
+  Item* items = nullptr;          // device, longest first
   Config cfg{};
   int grid = 0;
 };
 
 // Graphs cached per handle; beyond this many the oldest is dropped, so that
-// calls on ever new buffers do not accumulate graphs and order arrays.
+// calls on ever new buffers do not accumulate graphs and item arrays.
 constexpr size_t kMaxGraphs = 16;
 
 // Release one cached graph.  Its kernel arguments hold the workspace address
-// and its order array, so the caller has synchronised the device first.
+// and its item array, so the caller has synchronised the device first.
 void drop_graph(GraphEntry& g) {
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (g.graph) (void)hipGraphDestroy(g.graph);
-  if (g.order) (void)hipFree(g.order);
+  if (g.items) (void)hipFree(g.items);
   g = GraphEntry{};
 }
 
@@ -420,10 +427,10 @@ void save_tuned(State* st) {
       << "\"}\n";
 }
 
-int check_batch_args(const void* A, const int64_t* off, const int32_t* nd, const int32_t* nh,
-                     int32_t batch, int64_t k, int method, int dtype, void* out) {
+int check_batch_args(const void* A, const int64_t* off, const int32_t* nh, int32_t batch, int64_t k,
+                     int method, int dtype, void* out) {
   if (batch < 0) return batch_fail(NS_ERR_ARG, "batch < 0");
-  if (batch > 0 && (!A || !off || !nd || !nh || !out)) return batch_fail(NS_ERR_ARG, "null pointer");
+  if (batch > 0 && (!A || !off || !nh || !out)) return batch_fail(NS_ERR_ARG, "null pointer");
   if (k < 1) return batch_fail(NS_ERR_ARG, "k must be >= 1");
   if (dtype != NS_F32) return batch_fail(NS_ERR_UNSUPPORTED, "the batched form computes in FP32");
   if (method != NS_RADIX9 && method != NS_BINARY && method != NS_NAIVE)
@@ -440,14 +447,13 @@ int levels_for(int64_t k, int method, int32_t* levels) {
   return ns_plan(k, method, &ke, levels, &g);
 }
 
-BatchArgs make_args(State* st, const void* A, const int64_t* off, const int32_t* nd,
-                    const int32_t* order, int batch, int levels, int method, void* out) {
+BatchArgs make_args(State* st, const void* A, const int64_t* off, const Item* items, int batch,
+                    int levels, int method, void* out) {
   BatchArgs a{};
   a.A = static_cast<const float*>(A);
   a.out = static_cast<float*>(out);
   a.off = off;
-  a.nn = nd;
-  a.order = order;
+  a.items = items;
   a.batch = batch;
   a.levels = levels;
   a.method = method;
@@ -459,13 +465,15 @@ BatchArgs make_args(State* st, const void* A, const int64_t* off, const int32_t*
   return a;
 }
 
-int upload_order(const int32_t* n_host, int batch, int32_t** order_dev) {
-  std::vector<int32_t> order(batch);
-  for (int i = 0; i < batch; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return n_host[a] > n_host[b]; });   // longest first
-  B_HIP(hipMalloc(order_dev, std::max(1, batch) * sizeof(int32_t)));
-  if (batch) B_HIP(hipMemcpy(*order_dev, order.data(), batch * sizeof(int32_t), hipMemcpyHostToDevice));
+// The queue: (matrix, n) pairs in longest-first order, n from the validated
+// host array.
+int upload_items(const int32_t* n_host, int batch, Item** items_dev) {
+  std::vector<Item> items(batch);
+  for (int i = 0; i < batch; ++i) items[i] = Item{i, n_host[i]};
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item& a, const Item& b) { return a.n > b.n; });   // longest first
+  B_HIP(hipMalloc(items_dev, std::max(1, batch) * sizeof(Item)));
+  if (batch) B_HIP(hipMemcpy(*items_dev, items.data(), batch * sizeof(Item), hipMemcpyHostToDevice));
   return NS_OK;
 }
 
@@ -474,7 +482,8 @@ int upload_order(const int32_t* n_host, int batch, int32_t** order_dev) {
 int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, const int32_t* n_dev,
                  const int32_t* n_host, int32_t batch, int64_t k, int method, int dtype,
                  void* out_packed, hipStream_t stream, ns_report* rep) {
-  int rc = check_batch_args(A_packed, off_dev, n_dev, n_host, batch, k, method, dtype, out_packed);
+  (void)n_dev;   // not read: the queue carries the library's copy of n_host
+  int rc = check_batch_args(A_packed, off_dev, n_host, batch, k, method, dtype, out_packed);
   if (rc) return rc;
   int32_t levels;
   if ((rc = levels_for(k, method, &levels))) return rc;
@@ -487,16 +496,20 @@ int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, con
 
   const std::string hk = hist_key(n_host, batch);
   std::ostringstream ks;
-  ks << A_packed << '|' << out_packed << '|' << off_dev << '|' << n_dev << '|' << batch << '|'
-     << levels << '|' << method << '|' << hk;
+  ks << A_packed << '|' << out_packed << '|' << off_dev << '|' << batch << '|' << levels << '|'
+     << method << '|' << hk;
   const std::string key = ks.str();
   Config cfg{0, 2};
   auto tt = st->tuned.find(hk);
   if (tt != st->tuned.end()) cfg = tt->second;
 
   GraphEntry* ge = nullptr;
+  // a graph replays its item array, so the per-matrix n must match entry by
+  // entry, not only in histogram
   for (auto& g : st->graphs)
-    if (g.key == key && g.cfg.big == cfg.big && g.cfg.per_cu == cfg.per_cu) ge = &g;
+    if (g.key == key && g.cfg.big == cfg.big && g.cfg.per_cu == cfg.per_cu &&
+        std::equal(g.n_host.begin(), g.n_host.end(), n_host))
+      ge = &g;
   if (!ge) {
     if (st->graphs.size() >= kMaxGraphs) {
       B_HIP(hipDeviceSynchronize());             // the oldest graph may still be in flight
@@ -505,14 +518,15 @@ int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, con
     }
     GraphEntry g;
     g.key = key;
+    g.n_host.assign(n_host, n_host + batch);
     g.cfg = cfg;
     int per = 0;
     if ((rc = max_resident(cfg, &per))) return rc;
     const int resident = std::max(1, std::min(per, cfg.per_cu)) * st->cus;
     g.grid = std::max(1, std::min(batch, resident));
     if ((rc = ensure_slots(st, g.grid))) return rc;
-    if ((rc = upload_order(n_host, batch, &g.order))) return rc;
-    const BatchArgs a = make_args(st, A_packed, off_dev, n_dev, g.order, batch, levels, method, out_packed);
+    if ((rc = upload_items(n_host, batch, &g.items))) return rc;
+    const BatchArgs a = make_args(st, A_packed, off_dev, g.items, batch, levels, method, out_packed);
     // capture: zero the report accumulators (a kernel node), then the
     // persistent kernel; the queue counters are reset by the kernel itself
     B_HIP(hipStreamBeginCapture(st->capture, hipStreamCaptureModeThreadLocal));
@@ -553,7 +567,8 @@ int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, con
 int batched_autotune(ns_handle* h, const void* A_packed, const int64_t* off_dev,
                      const int32_t* n_dev, const int32_t* n_host, int32_t batch, int64_t k,
                      void* out_packed, hipStream_t stream, int32_t* n_timed) {
-  int rc = check_batch_args(A_packed, off_dev, n_dev, n_host, batch, k, NS_RADIX9, NS_F32, out_packed);
+  (void)n_dev;   // not read, as in batched_eval
+  int rc = check_batch_args(A_packed, off_dev, n_host, batch, k, NS_RADIX9, NS_F32, out_packed);
   if (rc) return rc;
   int32_t levels;
   if ((rc = levels_for(k, NS_RADIX9, &levels))) return rc;
@@ -563,43 +578,53 @@ int batched_autotune(ns_handle* h, const void* A_packed, const int64_t* off_dev,
   if ((rc = state_of(h, &st))) return rc;
   load_tuned(st);
   if (batch == 0) return NS_OK;
-  int32_t* order = nullptr;
-  if ((rc = upload_order(n_host, batch, &order))) return rc;
-  if (st->done_recorded) B_HIP(hipStreamWaitEvent(stream, st->done_ev, 0));
-  hipEvent_t e0, e1;
-  B_HIP(hipEventCreate(&e0));
-  B_HIP(hipEventCreate(&e1));
-  float best = 1e30f;
+  Item* items = nullptr;
+  if ((rc = upload_items(n_host, batch, &items))) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   Config best_cfg{0, 2};
   int timed = 0;
-  for (int big = 0; big < kNumBig; ++big) {
-    for (int per_cu = 1; per_cu <= 4; ++per_cu) {
-      Config c{big, per_cu};
-      int per = 0;
-      if ((rc = max_resident(c, &per))) return rc;
-      if (per_cu > per) continue;                    // not resident: skip
-      const int grid = std::max(1, std::min(batch, per_cu * st->cus));
-      if ((rc = ensure_slots(st, grid))) return rc;
-      const BatchArgs a = make_args(st, A_packed, off_dev, n_dev, order, batch, levels, NS_RADIX9, out_packed);
-      launch_batched(c, grid, a, stream);              // warm-up
-      B_HIP(hipEventRecord(e0, stream));
-      for (int r = 0; r < 3; ++r) launch_batched(c, grid, a, stream);
-      B_HIP(hipEventRecord(e1, stream));
-      B_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      B_HIP(hipEventElapsedTime(&ms, e0, e1));
-      ++timed;
-      if (ms < best) {
-        best = ms;
-        best_cfg = c;
+  // the timing loop; every exit from it goes through the release below
+  auto tune = [&]() -> int {
+    if (st->done_recorded) B_HIP(hipStreamWaitEvent(stream, st->done_ev, 0));
+    B_HIP(hipEventCreate(&e0));
+    B_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int big = 0; big < kNumBig; ++big) {
+      for (int per_cu = 1; per_cu <= 4; ++per_cu) {
+        Config c{big, per_cu};
+        int per = 0;
+        int r0;
+        if ((r0 = max_resident(c, &per))) return r0;
+        if (per_cu > per) continue;                    // not resident: skip
+        const int grid = std::max(1, std::min(batch, per_cu * st->cus));
+        if ((r0 = ensure_slots(st, grid))) return r0;
+        const BatchArgs a = make_args(st, A_packed, off_dev, items, batch, levels, NS_RADIX9, out_packed);
+        launch_batched(c, grid, a, stream);              // warm-up
+        B_HIP(hipEventRecord(e0, stream));
+        for (int r = 0; r < 3; ++r) launch_batched(c, grid, a, stream);
+        B_HIP(hipEventRecord(e1, stream));
+        B_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        B_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ++timed;
+        if (ms < best) {
+          best = ms;
+          best_cfg = c;
+        }
       }
     }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  B_HIP(hipFree(order));
-  B_HIP(hipEventRecord(st->done_ev, stream));
-  st->done_recorded = true;
+    B_HIP(hipEventRecord(st->done_ev, stream));
+    st->done_recorded = true;
+    return NS_OK;
+  };
+  rc = tune();
+  // the launches may still read the item array: wait before releasing it
+  const hipError_t se = hipStreamSynchronize(stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(items);
+  if (rc) return rc;
+  if (se != hipSuccess) return batch_fail(NS_ERR_HIP, "hipStreamSynchronize failed");
   st->tuned[hist_key(n_host, batch)] = best_cfg;
   save_tuned(st);
   if (n_timed) *n_timed = timed;

@@ -775,13 +775,30 @@ struct PolLow {
   using CT = float;
 };
 
+// 2^e for e in [-126, 127] (a normal float)
 __device__ __forceinline__ float pow2f(int e) { return __int_as_float((e + 127) << 23); }
 
-// exponent e with 2^e <= x < 2^(e+1) for the max-abs float bits (0 -> 0)
+// Exponent e with 2^e <= x < 2^(e+1) for the max-abs float bits (0 -> 0),
+// raised to at least kMinScaleExp.  An operand whose max-abs lies below
+// 2^kMinScaleExp (FP32 denormals included) is scaled as if it were
+// 2^kMinScaleExp: the operand scale 2^(14 - e) then stays at most 2^114, a
+// normal float, and the operand's entries land below 2^14 in FP16 (tiny ones
+// underflow there, as they would in any 16-bit format).  The largest e is 128
+// (an Inf or NaN max-abs), giving the normal scale 2^-114.
+constexpr int kMinScaleExp = -100;
 __device__ __forceinline__ int amax_exponent(const unsigned* amax) {
   if (!amax) return 0;
   const unsigned b = *amax;
-  return b ? (int)((b >> 23) & 0xff) - 127 : 0;
+  const int e = b ? (int)((b >> 23) & 0xff) - 127 : 0;
+  return e < kMinScaleExp ? kMinScaleExp : e;
+}
+
+// The product of two operands scaled by 2^(14 - ex) and 2^(14 - ey) is
+// unscaled by 2^(ex + ey - 28), applied with ldexp: ex + ey - 28 may fall
+// outside the normal exponent range (down to -228), where a formed power of two
+// would be wrong; ldexp rounds a result below FP32's range to a denormal or 0.
+__device__ __forceinline__ int unscale_exponent(const unsigned* xamax, const unsigned* yamax) {
+  return amax_exponent(xamax) + amax_exponent(yamax) - 28;
 }
 
 // split 8 floats into bf16 hi / lo (or scaled fp16 in `hi`)
@@ -830,12 +847,13 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs ar
   const float* __restrict__ Xp = static_cast<const float*>(args.X);
   const float* __restrict__ Yp = static_cast<const float*>(args.Y);
 
-  float sx = 1.f, sy = 1.f, unscale = 1.f;
+  float sx = 1.f, sy = 1.f;
+  int ush = 0;
   if constexpr (!Q::SPLIT) {
     const int ex = amax_exponent(args.epi->xamax), ey = amax_exponent(args.epi->yamax);
     sx = pow2f(14 - ex);
     sy = pow2f(14 - ey);
-    unscale = pow2f(ex - 14) * pow2f(ey - 14);
+    ush = ex + ey - 28;
   }
 
   // A items: consecutive threads take consecutive k-groups of a row (row-contiguous
@@ -957,7 +975,7 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs ar
 #pragma unroll
           for (int r = 0; r < 16; ++r)
             C[(32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * CPITCH + wn * Q::WTN + 32 * j + (lane & 31)] =
-                acc[i][j][r] * unscale;
+                ldexpf(acc[i][j][r], ush);
     }
     __syncthreads();
     for (int v = tid; v < Q::WTM * VPR; v += Q::THREADS) {

@@ -802,8 +802,9 @@ int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, co
       Buf U, X1, P, Q, T, P1, L2, R2, L3, R3, L4, R4, F;
       if (method == NS_RADIX9_RESID) { U = c.take(W64); X1 = c.take(W64); P = c.take(W64); Q = c.take(W64); T = c.take(W64); }
       if (method == NS_RADIX15 || method == NS_RADIX15C) {
-        if (method == NS_RADIX15) radix15_table(k15, nullptr, nullptr, nullptr);
-        else radix15c_table(k15, nullptr, nullptr, nullptr);
+        const bool ok = method == NS_RADIX15 ? radix15_table(k15, nullptr, nullptr, nullptr)
+                                             : radix15c_table(k15, nullptr, nullptr, nullptr);
+        if (!ok) return fail(NS_ERR_RANGE, "radix-15 coefficient polish did not converge");
         P1 = c.take(W64); L2 = c.take(W64); R2 = c.take(W64); L3 = c.take(W64);
         R3 = c.take(W64); L4 = c.take(W64); R4 = c.take(W64); F = c.take(W64);
       }

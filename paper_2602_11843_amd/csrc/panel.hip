@@ -56,11 +56,7 @@ __global__ __launch_bounds__(256) void to_panels_kernel(const float* __restrict_
     }
   }
   float scale = 1.f;
-  if constexpr (!SPLIT) {
-    const unsigned b = amax ? *amax : 0u;
-    const int e = b ? (int)((b >> 23) & 0xff) - 127 : 0;
-    scale = __int_as_float((14 - e + 127) << 23);
-  }
+  if constexpr (!SPLIT) scale = pow2f(14 - amax_exponent(amax));
   __syncthreads();
   const size_t plane = (size_t)n * n;
   const size_t nb16 = (size_t)(n / 16);
@@ -272,11 +268,8 @@ __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_panel_kernel(const M
   // epilogue: stage EFR fragment-rows of FP32 results at a time, then apply
   // the affine outputs with row-contiguous 16-byte vectors
   const GemmParams& p = *args.epi;
-  float unscale = 1.f;
-  if constexpr (!Q::SPLIT) {
-    const int ex = amax_exponent(p.xamax), ey = amax_exponent(p.yamax);
-    unscale = pow2f(ex - 14) * pow2f(ey - 14);
-  }
+  int ush = 0;
+  if constexpr (!Q::SPLIT) ush = unscale_exponent(p.xamax, p.yamax);
   const bool f32_out = all_f32(p);
   float* C = reinterpret_cast<float*>(smem);
   constexpr int VEC = 4, VPR = Q::BN / VEC;
@@ -295,7 +288,7 @@ __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_panel_kernel(const M
 #pragma unroll
           for (int r = 0; r < 16; ++r)
             C[(32 * (i % Q::EFR) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * Q::CPITCH + wn * Q::WTN +
-              32 * j + (lane & 31)] = acc[i][j][r] * unscale;
+              32 * j + (lane & 31)] = ldexpf(acc[i][j][r], ush);
       }
     }
     __syncthreads();

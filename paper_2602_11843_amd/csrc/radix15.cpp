@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 namespace ns {
 namespace {
@@ -63,9 +64,10 @@ void mul(const Poly& a, const Poly& b, Poly& out) {
 void axpy(R s, const Poly& x, Poly& y) { for (int i = 0; i < DEG; ++i) y.c[i] += s * x.c[i]; }
 
 // Evaluate the circuit at coefficients x: value of T15~ and d T15~ / d x_p.
-void circuit(const R* x, DPoly& T) {
-  static DPoly basis[6];
-  for (auto& b : basis) b.zero();
+// The basis is the caller's scratch (six DPoly, ~48 KB), so that concurrent
+// builds of the two tables share no state.
+void circuit(const R* x, DPoly* basis, DPoly& T) {
+  for (int i = 0; i < 6; ++i) basis[i].zero();
   basis[0].v.c[0] = 1;               // I
   basis[1].v.c[1] = 1;               // B
   basis[2].v.c[2] = 1;               // P1 = B^2
@@ -142,9 +144,12 @@ Table build(const double* start) {
   Table t{};
   R x[NP];
   for (int p = 0; p < NP; ++p) x[p] = start[p];
-  static DPoly T;
+  // heap scratch (about 55 KB), private to this build
+  std::vector<DPoly> scratch(7);
+  DPoly* basis = scratch.data();
+  DPoly& T = scratch[6];
   for (int it = 0; it < 30; ++it) {
-    circuit(x, T);
+    circuit(x, basis, T);
     R r[NEQ], rmax = 0;
     for (int j = 0; j < NEQ; ++j) {
       r[j] = T.v.c[j] - 1;
@@ -170,7 +175,7 @@ Table build(const double* start) {
     t.c[p] = (double)x[p];
     xd[p] = (R)t.c[p];
   }
-  circuit(xd, T);  // the rounded doubles, in extended precision
+  circuit(xd, basis, T);  // the rounded doubles, in extended precision
   R pe = 0;
   for (int j = 0; j < NEQ; ++j) pe = fmaxl(pe, fabsl(T.v.c[j] - 1));
   t.prefix_err = (double)pe;

@@ -22,3 +22,24 @@ def golden_rows(name):
             if line:
                 rows.append(line.split())
     return rows
+
+
+def close_report(got, ref):
+    """(relative Frobenius error, largest element error over the largest
+    reference element) of got against ref."""
+    import numpy as np
+    got = np.asarray(got, np.float64)
+    d = got - ref
+    return (float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            float(np.max(np.abs(d)) / np.max(np.abs(ref))))
+
+
+def assert_close(got, ref, tol, what=""):
+    """Both the relative Frobenius error and the element-wise error
+    max|got - ref| / max|ref| within tol; prints both."""
+    fro, elem = close_report(got, ref)
+    print(f"   {what} rel fro {fro:.3e}  max elem err / max|ref| {elem:.3e}  (tol {tol:g})",
+          flush=True)
+    assert fro < tol, (what, fro, tol)
+    assert elem < tol, (what, elem, tol)
+    return fro, elem

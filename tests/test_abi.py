@@ -152,3 +152,35 @@ def test_binding_refuses_bad_tensors_before_the_library(ns):
         ns.ns_eval_batched(buf.double(), torch.zeros(1, dtype=torch.int64), n, n, 81)
     with pytest.raises(ValueError):
         ns.ns_eval_batched_loop(buf, torch.zeros(1, dtype=torch.int64), n, 81)  # host memory
+
+
+def test_radix15_tables_built_concurrently_match():
+    """The two radix-15 tables are built on first use, each under its own
+    once-flag; first uses from two host threads at the same time must give
+    the tables a single thread gives.  A fresh process makes both calls the
+    first ones."""
+    import subprocess
+    import sys
+    code = r'''
+import threading, sys
+sys.path.insert(0, sys.argv[1])
+import paper_2602_11843_amd as ns
+out = {}
+go = threading.Barrier(2)
+def first(name, fn):
+    go.wait()
+    out[name] = fn()
+ts = [threading.Thread(target=first, args=(nm, fn)) for nm, fn in
+      (("b", ns.ns_radix15_coeffs), ("c", ns.ns_radix15c_coeffs))]
+for t in ts: t.start()
+for t in ts: t.join()
+print(repr(out["b"][0]))
+print(repr(out["c"][0]))
+'''
+    res = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True,
+                         timeout=300)
+    assert res.returncode == 0, res.stderr
+    got_b, got_c = (eval(line) for line in res.stdout.strip().splitlines())
+    for got, ref in ((got_b, coeffs15.polished()), (got_c, coeffs15.contract_polished())):
+        for a, b in zip(got, ref):
+            assert abs(a - b) <= 4 * abs(b) * 2.0 ** -52

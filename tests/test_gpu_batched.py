@@ -256,3 +256,43 @@ def test_jacobi_batch_workload(ns):
         worst = max(worst, series.rel_fro(G, ref))
     say(f"   worst rel err {worst:.3e}")
     assert worst < 1e-5
+
+
+def test_batched_reads_n_only_from_the_host_array(ns):
+    """The kernel takes each matrix's n from the library's own copy of n_host
+    (uploaded with the work queue); the device array n_dev is not read, so a
+    call without one gives the same bits."""
+    mats = mixed_batch(6)
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    h = ns.Handle(0)
+    a = ns.ns_eval_batched(A, offd, nd, nh, 81, "radix9", "f32", handle=h).clone()
+    b = ns.ns_eval_batched(A, offd, None, nh, 81, "radix9", "f32", handle=h)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    h.close()
+
+
+def test_graph_cache_keys_on_each_matrix_n(ns):
+    """Two calls on the same buffers with the same histogram of n but the
+    sizes in a different order: the second must not replay the first call's
+    queue.  (The buffers are sized for either assignment, so even a stale
+    queue would stay inside them.)"""
+    rng = np.random.default_rng(9)
+    m8, m16 = workloads.jacobi(8, rng), workloads.jacobi(16, rng)
+    A = torch.zeros(2 * 16 * 16, dtype=torch.float32, device="cuda")
+    out = torch.zeros_like(A)
+    offd = torch.zeros(2, dtype=torch.int64, device="cuda")
+    h = ns.Handle(0)
+    for order in ((m8, m16), (m16, m8)):
+        buf, offs = pack(order)
+        A.zero_()
+        A[:buf.size] = torch.from_numpy(buf).cuda()
+        offd.copy_(torch.from_numpy(offs))
+        nh = torch.tensor([M.shape[0] for M in order], dtype=torch.int32)
+        ns.ns_eval_batched(A, offd, None, nh, 81, "radix9", "f32", out_packed=out, handle=h)
+        torch.cuda.synchronize()
+        got = unpack(out.cpu().numpy(), offs, nh.numpy())
+        for M, G in zip(order, got):
+            ref, _ = series.radix9(M.astype(np.float32).astype(np.float64), 81)
+            assert series.rel_fro(G, ref) < 1e-5
+    h.close()

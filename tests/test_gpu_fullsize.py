@@ -1,12 +1,16 @@
 """GPU parity at the full n = 8192 workload sizes, in the launch configuration
-bench.py times, on sampled outputs the CPU can compute one by one.
+bench.py times.
 
-- precision_sym (symmetric, lam ~ U[-0.9, 0.9], k = 729): sampled columns of the
-  spectral definition Q diag((1 - lam^k)/(1 - lam)) Q^T.
+- precision_sym (symmetric, lam ~ U[-0.9, 0.9], k = 729): every output element
+  against the spectral definition Q diag((1 - lam^k)/(1 - lam)) Q^T (one
+  n^3 host product).
 - gaussian_rho (nonsymmetric, rho_hat 0.99, k = 3375): sampled columns of the
   closed form (I - A)^{-1} (I - A^k) from an FP64 LU factorisation, with A^k E
   formed by repeated squaring (A^4096 is still ~1e-9 in norm here: the
   power-iteration estimate sits slightly below the true spectral radius).
+  The FP32 legs are compared with the closed form for the FP32-rounded A that
+  the GPU receives, so that the input's rounding (amplified by the
+  conditioning of I - A) is not charged to the kernels.
 """
 
 import sys
@@ -15,6 +19,7 @@ import numpy as np
 import pytest
 
 import workloads
+from conftest import assert_close
 from oracle import series
 
 torch = pytest.importorskip("torch")
@@ -36,8 +41,9 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def precision_input():
-    say("[cpu] generating precision_sym n=8192")
-    return workloads.make("precision_sym")
+    say("[cpu] generating precision_sym n=8192 and its spectral definition at k=729")
+    w = workloads.make("precision_sym")
+    return w, series.spectral_form(w.Q, w.lam, 729)
 
 
 @pytest.mark.parametrize("method,dtype,tol", [
@@ -50,20 +56,19 @@ def precision_input():
     ("radix9_resid", "f16_scaled", 1e-6),
 ])
 def test_precision_workload(ns, precision_input, method, dtype, tol):
-    w = precision_input
+    w, ref = precision_input
     A = torch.from_numpy(w.A).cuda()
     if dtype == "f32":
         A = A.float()
     say(f"[gpu] precision_sym {method} {dtype} n=8192 k=729")
     out, rep = ns.ns_eval_ex(A, 729, method, dtype, report=True)
     torch.cuda.synchronize()
-    cols = np.sort(np.random.default_rng(1).choice(8192, 24, replace=False))
-    got = out[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
-    ref = series.spectral_form(w.Q, w.lam, rep["k_eff"], cols=cols)
-    err = series.rel_fro(got, ref)
-    say(f"   sampled rel err {err:.3e}")
-    assert err < tol
-    assert rep["gemms_performed"] == 15 and not rep["nonfinite"]
+    got = out.double().cpu().numpy()
+    del out, A
+    assert rep["gemms_performed"] == 15 and not rep["nonfinite"] and rep["k_eff"] == 729
+    # FP32: the reference is the FP64 definition for the unrounded A; with
+    # lam <= 0.9 the input's rounding contributes at most ~2^-24 / (1 - 0.9)
+    assert_close(got, ref, tol, f"{method} {dtype}")
 
 
 def powers_times(A, E, ks):
@@ -88,34 +93,38 @@ def gaussian_input():
     E = np.zeros((8192, len(cols)))
     E[cols, np.arange(len(cols))] = 1.0
     refs = {}
-    for rho, ks in ((0.99, (4096, 6561)), (0.95, (3375, 4096))):
+    for rho, ks in ((0.99, (3375, 4096, 6561)), (0.95, (3375, 4096))):
         A = g.A * (rho / 0.99)
         say(f"[cpu] closed-form reference rho={rho}: A^k E by squaring, LU of I - A")
         AkE = powers_times(A, E, ks)
-        lu = scipy.linalg.lu_factor(np.eye(8192) - A)
-        for k in ks:
-            refs[(rho, k)] = scipy.linalg.lu_solve(lu, E - AkE[k])
-        refs[(rho, None)] = scipy.linalg.lu_solve(lu, E)          # (I - A)^{-1}
-        del lu, A
+        for prec in ("f64", "f32"):
+            # the FP32 path receives A rounded to FP32: its reference is the
+            # closed form for that matrix.  A^k E is taken from the unrounded A
+            # for both: the rounding changes it by about k 2^-24 ||A^k||, below
+            # 1e-12 of the result, far under the FP32 bar
+            Ap = A if prec == "f64" else A.astype(np.float32).astype(np.float64)
+            lu = scipy.linalg.lu_factor(np.eye(8192) - Ap)
+            for k in ks:
+                refs[(prec, rho, k)] = scipy.linalg.lu_solve(lu, E - AkE[k])
+            refs[(prec, rho, None)] = scipy.linalg.lu_solve(lu, E)          # (I - A)^{-1}
+            del lu, Ap
+        del A
     return g, cols, refs
 
 
 @pytest.mark.parametrize("method,dtype,rho,tol,k", [
     ("radix9", "f64", 0.99, 1e-12, 3375),
     ("binary", "f64", 0.99, 1e-12, 3375),
-    # FP32 on this nonnormal, rho ~ 0.99 input: the powers grow transiently
-    # (||A^9||_F ~ 79) before decaying, and FP32 rounding is amplified by the
-    # conditioning of I - A; the measured errors are 9e-6 (binary) and 4e-5
-    # (radix-9), both far below the conditioning bound kappa * 2^-24
-    ("radix9", "f32", 0.99, 1e-4, 3375),
-    ("binary", "f32", 0.99, 1e-4, 3375),
+    ("radix9", "f32", 0.99, 1e-5, 3375),
+    ("binary", "f32", 0.99, 1e-5, 3375),
+    ("mixed", "f32", 0.99, 1e-5, 3375),
     ("radix15", "f32", 0.95, 1e-5, 3375),
     ("radix15", "f64", 0.95, 1e-12, 3375),
     # the contraction-aware table converges at rho 0.99 as well.  In FP64 one
     # more level is used: at t = 3 the residual E^[3](A) is still ~6e-9 in
     # Frobenius norm on this nonnormal matrix (R_2 has norm 1.6 though its
     # spectral radius is below 0.1), so Y_3 differs from (I - A)^{-1} by ~1e-9
-    ("radix15c", "f32", 0.99, 1e-4, 3375),
+    ("radix15c", "f32", 0.99, 1e-5, 3375),
     ("radix15c", "f64", 0.99, 1e-12, 15 ** 4),
 ])
 def test_gaussian_workload(ns, gaussian_input, method, dtype, rho, tol, k):
@@ -132,9 +141,8 @@ def test_gaussian_workload(ns, gaussian_input, method, dtype, rho, tol, k):
     # with the contraction-aware table at rho 0.99, E^[3](A) is the final
     # residual (level norm ~1e-13), so Y_3 is compared with (I - A)^{-1}
     k_ref = {"radix15": 3375, "radix15c": None}.get(method, rep["k_eff"])
-    err = series.rel_fro(got, refs[(rho, k_ref)])
-    say(f"   sampled rel err vs closed form {err:.3e}; level norms {['%.3g' % x for x in rep['level_norm']]}")
-    assert err < tol
+    say(f"   level norms {['%.3g' % x for x in rep['level_norm']]}")
+    assert_close(got, refs[(dtype, rho, k_ref)], tol, f"{method} {dtype} rho={rho} (sampled columns)")
     # the last level's norm (power or residual) is far below the first; an FP32
     # residual recomputed as I - Y + A Y stops at its rounding floor (~1e-3 in
     # Frobenius norm at n = 8192 with this conditioning)

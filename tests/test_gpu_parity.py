@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads
+from conftest import assert_close
 from oracle import series
 
 torch = pytest.importorskip("torch")
@@ -67,9 +68,7 @@ def test_small_parity(ns, method, dtype, n):
     k = 20 if method == "naive" else 81
     got, rep = run(ns, w.A, k, method, dtype)
     ref, orep = series.evaluate(oracle_input(w.A, dtype), k, ORACLE_NAME[method])
-    err = series.rel_fro(got, ref)
-    say(f"   rel err {err:.3e}")
-    assert err < TOL[dtype]
+    assert_close(got, ref, TOL[dtype], f"{method} {dtype} n={n}")
     assert rep["k_eff"] == orep["k_eff"]
     assert rep["gemms_performed"] == rep["gemms_formula"] == orep["products"]
     assert not rep["nonfinite"]
@@ -94,10 +93,9 @@ def test_splitk_range_parity(ns, method, n):
     k = 20 if method == "naive" else 81
     got, rep = run(ns, w.A, k, method, "f64")
     ref, orep = series.evaluate(w.A, k, ORACLE_NAME[method])
-    err = series.rel_fro(got, ref)
-    say(f"   rel err {err:.3e}  n_internal {rep['n_internal']}")
+    say(f"   n_internal {rep['n_internal']}")
     assert rep["n_internal"] in (160, 224, 256)
-    assert err < TOL["f64"]
+    assert_close(got, ref, TOL["f64"], f"{method} n={n}")
     assert not rep["nonfinite"]
 
 
@@ -108,7 +106,7 @@ def test_nonsymmetric_parity(ns, method, dtype):
     k = 225 if method == "radix15" else 81
     got, _ = run(ns, g.A, k, method, dtype)
     ref, _ = series.evaluate(oracle_input(g.A, dtype), k, method)
-    assert series.rel_fro(got, ref) < TOL[dtype]
+    assert_close(got, ref, TOL[dtype], f"{method} {dtype} nonsymmetric")
 
 
 # --- the n = 256, k = 81 workload in full --------------------------------------
@@ -119,8 +117,8 @@ def test_small_symmetric_workload(ns, method):
     got, rep = run(ns, w.A, 81, method, "f64")
     ref, _ = series.evaluate(w.A, 81, method)
     closed = series.spectral_form(w.Q, w.lam, rep["k_eff"])
-    assert series.rel_fro(got, ref) < 1e-12
-    assert series.rel_fro(got, closed) < 1e-12
+    assert_close(got, ref, 1e-12, f"{method} vs oracle")
+    assert_close(got, closed, 1e-12, f"{method} vs closed form")
 
 
 # --- edge cases -------------------------------------------------------------
@@ -149,7 +147,7 @@ def test_leading_dimension(ns):
     ns.ns_eval_ex(big[:, :100], 81, "radix9", "f64", out=out[:, :100])
     torch.cuda.synchronize()
     ref, _ = series.radix9(w.A, 81)
-    assert series.rel_fro(out[:, :100].cpu().numpy(), ref) < 1e-12
+    assert_close(out[:, :100].cpu().numpy(), ref, 1e-12, "lda/ldo > n")
     assert torch.all(out[:, 100:] == 7.0)          # nothing written past ldo's n columns
 
 
@@ -279,37 +277,44 @@ def test_element_offsets_past_2_31(ns, dtype):
     torch.cuda.empty_cache()
 
 
+@pytest.fixture(scope="module")
+def large_symmetric():
+    say("[cpu] generating large_symmetric n=4096")
+    return workloads.make("large_symmetric")
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("method", ["binary", "radix9"])
-def test_large_symmetric_sampled_columns(ns, method, dtype):
-    """n = 4096, k = 729 (the benchmarked configuration): 24 sampled columns
-    against the spectral closed form Q diag((1 - lam^k)/(1 - lam)) Q^T."""
-    w = workloads.make("large_symmetric")
+def test_large_symmetric_full(ns, large_symmetric, method, dtype):
+    """n = 4096, k = 729 (the benchmarked configuration, large tiles of both
+    engines): every output element against the oracle's own schedule on the
+    input the GPU receives, and (FP64) against the spectral definition."""
+    w = large_symmetric
     got, rep = run(ns, w.A, 729, method, dtype)
-    rng = np.random.default_rng(0)
-    cols = np.sort(rng.choice(4096, 24, replace=False))
-    # for FP32 the reference is still the FP64 definition for the unrounded A:
-    # rounding the input to FP32 is part of that path's error
-    ref = series.spectral_form(w.Q, w.lam, rep["k_eff"], cols=cols)
-    err = series.rel_fro(got[:, cols], ref)
-    say(f"   sampled rel err {err:.3e}")
-    assert err < TOL[dtype]
+    say("[cpu] oracle schedule at n=4096")
+    ref, orep = series.evaluate(oracle_input(w.A, dtype), 729, method)
+    assert rep["gemms_performed"] == orep["products"]
+    assert_close(got, ref, TOL[dtype], f"{method} {dtype} vs oracle")
+    if dtype == "f64":
+        assert_close(got, series.spectral_form(w.Q, w.lam, rep["k_eff"]), TOL[dtype],
+                     "vs spectral definition")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", [2100, 3000])
-def test_mid_sizes_sampled_columns(ns, n, dtype):
+def test_mid_sizes_full(ns, n, dtype):
     """Sizes between the small and the large tiles (FP32 keeps its small tile
-    up to 4096, FP64 switches at 2048), with a ragged tail: 16 sampled columns
+    up to 4096, FP64 switches at 2048), with a ragged tail: the whole result
     against the spectral closed form."""
     w = workloads.symmetric(n, 0.9, 40 + n)
     got, rep = run(ns, w.A, 81, "radix9", dtype)
-    cols = np.sort(np.random.default_rng(1).choice(n, 16, replace=False))
-    cols[-1] = n - 1
-    ref = series.spectral_form(w.Q, w.lam, rep["k_eff"], cols=cols)
-    err = series.rel_fro(got[:, cols], ref)
-    say(f"   sampled rel err {err:.3e}  n_internal {rep['n_internal']}")
-    assert err < TOL[dtype]
+    say(f"   n_internal {rep['n_internal']}")
+    ref = series.spectral_form(w.Q, w.lam, rep["k_eff"])
+    # FP32: the reference is the FP64 definition for the unrounded A, so the
+    # input's rounding to FP32 is part of the error here (lam <= 0.9 keeps
+    # its amplification to ~1/(1 - 0.9))
+    assert_close(got, ref, TOL[dtype], f"radix9 {dtype} n={n}")
 
 
 # --- exact S_k for any k (no round-up) ---------------------------------------
@@ -328,9 +333,8 @@ def test_mixed_any_k_parity(ns, dtype, n):
     for k in MIXED_KS:
         got, rep = run(ns, g.A, k, "mixed", dtype)
         ref, orep = series.mixed(oracle_input(g.A, dtype), k)
-        err = series.rel_fro(got, ref)
-        say(f"   k={k} rel err {err:.3e} products {rep['gemms_performed']}")
-        assert err < TOL[dtype], (k, err)
+        say(f"   k={k} products {rep['gemms_performed']}")
+        assert_close(got, ref, TOL[dtype], f"mixed {dtype} k={k}")
         assert rep["k_eff"] == k
         assert rep["gemms_performed"] == rep["gemms_formula"] == orep["products"]
         assert rep["levels"] == orep["levels"]
@@ -347,4 +351,4 @@ def test_mixed_matches_closed_form_at_k_not_a_power(ns):
         got, rep = run(ns, w.A, k, "mixed", "f64")
         closed = series.spectral_form(w.Q, w.lam, k)
         assert rep["k_eff"] == k
-        assert series.rel_fro(got, closed) < 1e-12, k
+        assert_close(got, closed, 1e-12, f"mixed k={k} vs closed form")
