@@ -1,25 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark: S_k(A) time and GEMM TFLOP/s on one MI355X.
 
-Default workload (one step = one evaluation of S_k(A)):
-    large_symmetric: n = 4096, k = 729 = 9^3, A = Q diag(lam) Q^T with
-    lam ~ U[-0.95, 0.95], seed 2; radix-9 (15 products) in FP64.
-In the same run, with the same protocol: binary splitting (20 products,
-k_eff = 1024) in FP64, and both methods in FP32.
+One step = one evaluation of S_k(A).  The headline (the JSON line's `value`)
+is the largest single-GPU configuration:
 
-`value` is logical GEMM TFLOP/s of the radix-9 FP64 step: (products x 2 n^3)
-/ step time, inputs resident in HBM before the timed region.  The JSON line
-also carries the per-launch roofline of the FP64 product kernel (HIP events
-around every product launch on the call's stream during the timed steps) and
-the CPU oracle timed on the host's cores.
+    precision_sym: n = 8192, k = 729 = 9^3, A = Q diag(lam) Q^T with
+    lam ~ U[-0.9, 0.9], seed 4; radix-9 (15 products) with every product on
+    FP64 MFMA.  Its squaring baseline is binary splitting (20 products,
+    k_eff = 1024) in FP64 on the same input.
 
-Other workloads (`--workload`): gaussian_rho (n = 8192 FP32, k = 3375,
-radix-15 vs radix-9 vs binary), precision_sym (n = 8192, k = 729, mixed
-precision forms), jacobi_batch (2048 small matrices, persistent batched
-launch vs per-matrix loop).  Each prints its own JSON line.
+`value` is logical GEMM TFLOP/s of the headline step: (products x 2 n^3) /
+step time, inputs resident in HBM before the timed region.  The line also
+carries, measured with the same protocol (warm-up calls, then `steps` timed
+calls bracketed by device synchronisation) and each with its own roofline,
+the legs of the other workloads:
+
+  precision_sym   radix-9 in FP32, FP32 + FP64 sum, split-BF16, scaled FP16;
+                  the residual forms (FP64 residual) in split-BF16, scaled
+                  FP16 and FP32
+  gaussian_rho    n = 8192 FP32, nonsymmetric, rho_hat = 0.99, k = 3375:
+                  radix-15 (contraction-aware table and App. B table),
+                  radix-9 (k_eff 6561), binary (k_eff 4096), the exact any-k
+                  plan, and the contraction-aware radix-15 with FP32 products
+                  and an FP64 residual; level norms per leg; the App. B
+                  table again at rho_hat = 0.95
+  large_symmetric n = 4096, k = 729: radix-9 and binary in FP64 and FP32
+  jacobi_batch    2048 small FP32 matrices, k = 81 radix-9: one persistent
+                  graph launch against the per-matrix launch loop
+  small_symmetric n = 256 FP64, k = 81: radix-9, binary, naive; time per
+                  product launch and the critical path in launches
+
+Every leg's roofline comes from HIP events recorded by the library around each
+product launch on the call's stream, per product engine.  The CPU oracle
+(test infrastructure) is timed on a bounded sample on the host's cores.
+`--workload NAME` runs one workload and prints its own line.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,8 +47,11 @@ import time
 import numpy as np
 
 METRIC = "S_k(A) time + GEMM TFLOP/s (%MFMA peak), radix-9/15 vs squaring at stated err"
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6}   # dense TFLOP/s, MI355X
-HBM_PEAK_GBS = 8000.0
+PEAK = {"f64": 78.6, "f32": 157.3, "split_bf16": 2516.6, "f16_scaled": 2516.6}   # dense, MI355X
+# MFMA work per logical product on each engine (split-BF16: three BF16 products)
+MFMA_PER_LOGICAL = {"f64": 1.0, "f32": 1.0, "split_bf16": 3.0, "f16_scaled": 1.0}
+ENGINES = ("f64", "f32", "split_bf16", "f16_scaled")
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def log(*a):
@@ -42,11 +63,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large_symmetric",
-                    choices=["large_symmetric", "gaussian_rho", "precision_sym", "jacobi_batch",
-                             "small_symmetric", "all"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "precision_sym", "gaussian_rho", "large_symmetric",
+                             "jacobi_batch", "small_symmetric"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip timing the CPU oracle (profiling runs)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the accuracy checks against host references (profiling runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--only", default="",
@@ -54,11 +77,84 @@ def parse():
     return ap.parse_args()
 
 
+# ---------------------------------------------------------------------------
+# rooflines
+# ---------------------------------------------------------------------------
+
+def kernel_name(engine, n):
+    """The product kernel an engine runs at padded size n."""
+    if engine == "f64":
+        if n >= 2048:
+            return "gemm_kernel<PolF64M16<2,2,4,4>>"
+        if 160 <= n <= 256:
+            return "gemm_f64_splitk_kernel"
+        return "gemm_kernel<PolF64M16<2,2,1,1,4>>"
+    if engine == "f32":
+        return "gemm_kernel<PolF32<2,2,4,8>>" if n >= 4096 else "gemm_kernel<PolF32<2,2,2,2>>"
+    if engine == "split_bf16":
+        return ("gemm_panel_kernel<PolPanel<2,4,4,2,true,1,2,2>>" if n >= 3072
+                else "gemm_lowp_kernel<PolLow<2,2,1,1,true>>")
+    return ("gemm_panel_kernel<PolPanel<2,4,4,2,false,1,2,2>>" if n >= 2560
+            else "gemm_lowp_kernel<PolLow<2,2,1,1,false>>")
+
+
+def engine_roofline(engine, stats, n):
+    """Roofline of one engine's product launches: MFMA work per launch (2 n^3
+    per logical product, times 3 for split-BF16) over the launches' average
+    duration, against that engine's dense MFMA peak."""
+    cnt, ms, flops = stats
+    if not cnt or ms <= 0:
+        return None
+    mfma = MFMA_PER_LOGICAL[engine]
+    achieved = mfma * flops / (ms * 1e-3) / 1e12
+    peak = PEAK[engine]
+    return {"bound": "mfma", "kernel": kernel_name(engine, n), "achieved": round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "per_launch_flops": mfma * flops / cnt, "avg_launch_ms": round(ms / cnt, 5),
+            "launches": cnt}
+
+
+KERNEL_SOURCES = ("gemm_device.h", "gemm.hip", "common.h")
+
+
+def kernel_source_hash(root=None):
+    """Hash of the FP64/FP32 product kernels' sources: a counter summary taken
+    on other sources no longer describes the kernel."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root or ROOT, "paper_2602_11843_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(summary, root=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary under
+    profiles/, or None when the summary is missing or was taken on other
+    kernel sources (it records their hash)."""
+    path = os.path.join(root or ROOT, "profiles", summary)
+    try:
+        vals = {}
+        with open(path) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 2 and parts[0] in ("source_sha256_16", "traffic_bytes_per_launch"):
+                    vals[parts[0]] = parts[1]
+        if vals.get("source_sha256_16") != kernel_source_hash(root):
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
+
 def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate_events=False):
-    """Time `steps` evaluations after `warmup`; per-product HIP-event timing
-    on the call's stream during the timed steps.  separate_events: the timed
-    steps run without the events (at small n the event records between
-    launches are a large part of a call), and a second pass of as many steps
+    """Time `steps` evaluations after `warmup`.  Per-launch HIP events on the
+    call's stream are recorded during the timed steps; with separate_events
+    the timed steps run without them (at small n the event records between
+    launches are a visible part of a call) and a second pass of as many steps
     records them for the per-launch figures."""
     import torch
     k_eff, levels, products = ns.ns_plan(k, method)
@@ -81,22 +177,46 @@ def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate
         for _ in range(steps):
             fn()
         torch.cuda.synchronize()
+    per_engine = {e: h.ns_product_timing_dtype(e) for e in ENGINES}
     cnt, kms, kfl = h.ns_product_timing(reset=True)
     h.ns_set_product_timing(False)
+    _, rep = ns.ns_eval_ex(A, k, method, dtype, out=out, handle=h, stream=stream, report=True)
     flops = products * 2.0 * n ** 3
-    peak = PEAK["f64" if dtype == "f64" else ("bf16" if dtype in ("split_bf16", "f16_scaled") else "f32")]
+    rooflines = {e: engine_roofline(e, st, rep["n_internal"]) for e, st in per_engine.items() if st[0]}
+    dominant = max(rooflines, key=lambda e: per_engine[e][1]) if rooflines else None
     r = {"ms": sec * 1e3, "tflops": flops / sec / 1e12, "products": products, "k_eff": k_eff,
-         "pct_peak_of_dtype": 100.0 * flops / sec / 1e12 / peak,
-         "product_launches": cnt, "product_avg_ms": kms / max(cnt, 1),
-         "product_tflops": kfl / (kms * 1e-3) / 1e12 if kms > 0 else None}
-    log(f"[bench]   {sec * 1e3:.2f} ms/step  {flops / sec / 1e12:.2f} TFLOP/s  "
-        f"product avg {kms / max(cnt, 1):.3f} ms")
+         "levels": levels, "product_launches_per_call": rep["product_launches"],
+         "launches_timed": cnt, "kernel_ms_per_call": kms / steps,
+         "roofline": rooflines.get(dominant), "rooflines_by_engine": rooflines,
+         "level_norm": rep["level_norm"], "nonfinite": rep["nonfinite"]}
+    log(f"[bench]   {sec * 1e3:.3f} ms/step  {flops / sec / 1e12:.2f} TFLOP/s logical; "
+        + "; ".join(f"{e} {v['avg_launch_ms']:.4f} ms/launch {v['frac']:.3f} of peak"
+                    for e, v in rooflines.items()))
     return r
 
 
 def rnd(d):
-    return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()}
+    out = {}
+    for k, v in d.items():
+        if isinstance(v, float):
+            out[k] = round(v, 6)
+        elif isinstance(v, dict):
+            out[k] = rnd(v)
+        else:
+            out[k] = v
+    return out
 
+
+def select(legs, args):
+    if not args.only:
+        return legs
+    want = [tuple(x.split(":")) for x in args.only.split(",")]
+    return [l for l in legs if l[:2] in want]
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle baseline
+# ---------------------------------------------------------------------------
 
 def blas_threads():
     try:
@@ -120,11 +240,6 @@ def cpu_model():
     return "unknown"
 
 
-def sampled_cols(n, count, seed=0):
-    rng = np.random.default_rng(seed)
-    return np.sort(rng.choice(n, count, replace=False))
-
-
 def cpu_oracle_sample(fn, label, flops, min_seconds=10.0, max_runs=50):
     """Time the oracle (test/benchmark infrastructure) on a bounded sample:
     `fn` (worth `flops`) is run until at least min_seconds have passed (at
@@ -146,61 +261,121 @@ def cpu_oracle_sample(fn, label, flops, min_seconds=10.0, max_runs=50):
                  "sample": f"{label}: {runs} run(s), {sec:.2f} s each, {total:.1f} s in all ({cpu_model()})"}
 
 
-def measured_traffic(summary="pmc_product_f64_large_symmetric.md", root=None):
-    """HBM-side bytes per launch of the FP64 product kernel from the committed
-    rocprofv3 counter summary, or None once the kernel source or the product
-    schedule (which sets each launch's epilogue) has changed since the
-    counters were taken (the summary records a source hash)."""
-    import hashlib
-    root = root or os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", summary)
-    try:
-        vals = {}
-        with open(path) as fh:
-            for line in fh:
-                parts = line.split()
-                if len(parts) == 2 and parts[0] in ("source_sha256_16", "traffic_bytes_per_launch"):
-                    vals[parts[0]] = parts[1]
-        h = hashlib.sha256()
-        for f in ("gemm_device.h", "gemm.hip", "ns.cpp"):
-            with open(os.path.join(root, "paper_2602_11843_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
-        if vals.get("source_sha256_16") != h.hexdigest()[:16]:
-            return None
-        return float(vals["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+def close(got, ref):
+    """(relative Frobenius error, max element error / max |ref|)."""
+    d = np.asarray(got, np.float64) - ref
+    return (float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            float(np.max(np.abs(d)) / np.max(np.abs(ref))))
 
 
-def roofline_from_leg(leg, n, kernel, dtype, mfma_per_logical=1.0):
-    if not leg.get("product_launches"):
-        return None
-    peak = PEAK[dtype]
-    achieved = mfma_per_logical * 2.0 * n ** 3 / (leg["product_avg_ms"] * 1e-3) / 1e12
-    return {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "per_launch_flops": mfma_per_logical * 2.0 * n ** 3,
-            "avg_launch_ms": round(leg["product_avg_ms"], 5), "launches": leg["product_launches"]}
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def bench_precision_sym(args, torch, ns):
+    """n = 8192, k = 729, symmetric lam ~ U[-0.9, 0.9]: radix-9 with every
+    product in FP64 (the headline) against binary splitting in FP64, and
+    radix-9 in the precision forms."""
+    import workloads
+    from oracle import series                      # benchmark infrastructure only
+    log("[bench] generating precision_sym input (n=8192)")
+    w = workloads.make("precision_sym")
+    n, k = w.A.shape[0], 729
+    ref = None if args.no_check else series.spectral_form(w.Q, w.lam, k)
+    ref_bin = None if args.no_check else series.spectral_form(w.Q, w.lam, 1024)
+    h = ns.Handle(0)
+    stream = torch.cuda.current_stream()
+    A64 = torch.from_numpy(w.A).cuda()
+    A32 = A64.float()
+    out64, out32 = torch.empty_like(A64), torch.empty_like(A32)
+    legs = select([("radix9", "f64"), ("binary", "f64"), ("radix9", "f32"), ("radix9", "f32_acc64"),
+                   ("radix9", "split_bf16"), ("radix9", "f16_scaled"),
+                   ("radix9_resid", "split_bf16"), ("radix9_resid", "f16_scaled"),
+                   ("radix9_resid", "f32_acc64")], args)
+    res = {}
+    for method, dtype in legs:
+        A, out = (A32, out32) if dtype == "f32" else (A64, out64)
+        r = time_leg(ns, h, A, k, method, dtype, out, args.steps, args.warmup, stream, n)
+        if ref is not None:
+            got = out.double().cpu().numpy()
+            r["rel_err_vs_definition"], r["max_elem_err_vs_definition"] = close(
+                got, ref_bin if method == "binary" else ref)
+            del got
+            log(f"[bench]   rel err vs FP64 definition {r['rel_err_vs_definition']:.3e}")
+        res[f"{method}:{dtype}"] = r
+    cpu = None
+    if not args.no_cpu_baseline:
+        _, cpu = cpu_oracle_sample(lambda: series.radix9(w.A, 9),
+                                   "one radix-9 level of the oracle at n=8192 (5 float64 products)",
+                                   5 * 2.0 * n ** 3)
+    del A64, A32, out64, out32
+    h.close()
+    torch.cuda.empty_cache()
+    info = {"workload": "precision_sym", "n": n, "k": k, "seed": w.seed, "lam": "U[-0.9,0.9]"}
+    return res, cpu, info
 
 
-def base_line(args, value, ms, dtype, config):
-    return {"metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
-            "data": "synthetic", "config": config}
-
-
-def select(legs, args):
-    if not args.only:
-        return legs
-    want = [tuple(x.split(":")) for x in args.only.split(",")]
-    return [l for l in legs if l in want]
+def bench_gaussian_rho(args, torch, ns):
+    """n = 8192 FP32, nonsymmetric N(0,1)/sqrt(n) scaled to rho_hat = 0.99,
+    k = 3375: radix-15 (contraction-aware and App. B tables, 18 products)
+    against radix-9 (20, k_eff 6561), binary (24, k_eff 4096) and the exact
+    any-k plan (19); the contraction-aware radix-15 with FP32 products and an
+    FP64 residual; the App. B table again at rho_hat = 0.95."""
+    import scipy.linalg
+    import workloads
+    log("[bench] generating gaussian_rho input (n=8192, 400 power iterations)")
+    g = workloads.make("gaussian_rho")
+    n, k = g.A.shape[0], 3375
+    h = ns.Handle(0)
+    stream = torch.cuda.current_stream()
+    cols = np.sort(np.random.default_rng(0).choice(n, 16, replace=False))
+    I_cols = np.zeros((n, len(cols)))
+    I_cols[cols, np.arange(len(cols))] = 1.0
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    out64 = None
+    res = {}
+    for rho in (0.99, 0.95):
+        A = g.A * (rho / 0.99)
+        refs = {}
+        if not args.no_check:
+            # S_inf columns (I - A)^{-1} e_j, for the FP32-rounded A (what the
+            # FP32 path receives) and the FP64 A; A^k is below 1e-8 here
+            for prec in ("f32", "f64"):
+                Ap = A.astype(np.float32).astype(np.float64) if prec == "f32" else A
+                log(f"[bench] LU reference (I - A)^-1 e_j for rho {rho} ({prec} input)")
+                refs[prec] = scipy.linalg.lu_solve(scipy.linalg.lu_factor(np.eye(n) - Ap), I_cols)
+        A32 = torch.from_numpy(A).float().cuda()
+        A64 = torch.from_numpy(A).cuda()
+        legs = ([("radix15c", "f32"), ("radix15", "f32"), ("radix9", "f32"), ("binary", "f32"),
+                 ("mixed", "f32"), ("radix15c", "f32_acc64")] if rho == 0.99 else [("radix15", "f32")])
+        for method, dtype in select(legs, args):
+            if dtype == "f32":
+                Ad, o = A32, out
+            else:
+                out64 = out64 if out64 is not None else torch.empty((n, n), dtype=torch.float64,
+                                                                    device="cuda")
+                Ad, o = A64, out64
+            r = time_leg(ns, h, Ad, k, method, dtype, o, args.steps, args.warmup, stream, n)
+            if refs:
+                got = o[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
+                r["rel_err_sampled_vs_inverse"], r["max_elem_err_sampled_vs_inverse"] = close(
+                    got, refs["f32" if dtype == "f32" else "f64"])
+                log(f"[bench]   rho {rho} {method} {dtype}: sampled rel err vs (I-A)^-1 "
+                    f"{r['rel_err_sampled_vs_inverse']:.3e}, level norms "
+                    f"{['%.3g' % x for x in r['level_norm']]}")
+            res[f"{method}:{dtype}:rho{rho}"] = r
+        del A32, A64
+    h.close()
+    del out, out64
+    torch.cuda.empty_cache()
+    info = {"workload": "gaussian_rho", "n": n, "k": k, "rho_hat": 0.99, "seed": g.seed}
+    return res, None, info
 
 
 def bench_large_symmetric(args, torch, ns):
-    """n = 4096, k = 729: radix-9 vs binary in FP64 and FP32 (the headline)."""
+    """n = 4096, k = 729: radix-9 against binary in FP64 and FP32."""
     import workloads
-    from oracle import series                      # benchmark infrastructure only
+    from oracle import series
     w = workloads.make("large_symmetric")
     n, k = w.A.shape[0], 729
     h = ns.Handle(0)
@@ -209,155 +384,19 @@ def bench_large_symmetric(args, torch, ns):
     A32 = A64.float()
     out64, out32 = torch.empty_like(A64), torch.empty_like(A32)
     legs = select([("radix9", "f64"), ("binary", "f64"), ("radix9", "f32"), ("binary", "f32")], args)
-    res, errs = {}, {}
-    cols = sampled_cols(n, 64)
+    cols = np.sort(np.random.default_rng(0).choice(n, 64, replace=False))
+    res = {}
     for method, dtype in legs:
         A, out = (A64, out64) if dtype == "f64" else (A32, out32)
-        res[(method, dtype)] = time_leg(ns, h, A, k, method, dtype, out, args.steps, args.warmup,
-                                        stream, n)
-        got = out.double().cpu().numpy()
-        ref = series.spectral_form(w.Q, w.lam, res[(method, dtype)]["k_eff"], cols=cols)
-        errs[(method, dtype)] = series.rel_fro(got[:, cols], ref)
-    key = ("radix9", "f64") if ("radix9", "f64") in res else next(iter(res))
-    main = res[key]
-    cpu, err_full = None, None
-    if not args.no_cpu_baseline:
-        S_cpu, cpu = cpu_oracle_sample(lambda: series.radix9(w.A, k)[0],
-                                       "whole workload once: radix-9 S_729(A), n=4096, 15 float64 products",
-                                       15 * 2.0 * n ** 3)
-        if ("radix9", "f64") in res:
-            ns.ns_eval_ex(A64, k, "radix9", "f64", out=out64, handle=h, stream=stream)
-            torch.cuda.synchronize()
-            err_full = series.rel_fro(out64.cpu().numpy(), S_cpu)
-    line = base_line(args, main["tflops"], main["ms"], key[1],
-                     {"workload": "large_symmetric", "n": n, "k": k, "method": key[0],
-                      "k_eff": main["k_eff"], "products": main["products"], "seed": w.seed,
-                      "lam": "U[-0.95,0.95]"})
-    line["pct_mfma_peak"] = round(100.0 * main["tflops"] / PEAK[key[1]], 2)
-    line["rel_err_vs_definition_sampled"] = errs[key]
-    line["rel_err_vs_cpu_oracle"] = err_full
-    line["legs"] = {f"{m}:{d}": {**rnd(r), "rel_err_sampled": errs[(m, d)]} for (m, d), r in res.items()}
-    for d in ("f64", "f32"):
-        if ("radix9", d) in res and ("binary", d) in res:
-            line[f"radix9_over_binary_speedup_{d}"] = round(res[("binary", d)]["ms"] / res[("radix9", d)]["ms"], 4)
-    line["predicted_speedup_by_product_count"] = round(20 / 15, 4)
-    kern = "gemm_kernel<PolF64M16<2,2,4,4>>" if key[1] == "f64" else "gemm_kernel<PolF32<2,2,4,8>>"
-    line["roofline"] = roofline_from_leg(main, n, kern, key[1])
-    if line["roofline"] and key == ("radix9", "f64"):
-        line["roofline"]["traffic"] = measured_traffic()
-        line["roofline"]["traffic_unit"] = "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)"
-    line["cpu_baseline"] = cpu
-    return line
-
-
-def bench_gaussian_rho(args, torch, ns):
-    """n = 8192 FP32, nonsymmetric N(0,1)/sqrt(n) scaled to rho_hat = 0.99,
-    k = 3375: radix-15 with the contraction-aware table (18 products, the
-    reported value) and with the App. B table (18, diverges here) vs radix-9
-    (20, k_eff 6561) vs binary (24, k_eff 4096) vs the exact any-k plan (19,
-    k itself), with per-level norms; plus the same matrix rescaled to
-    rho_hat = 0.95, inside the App. B kernel's convergence domain."""
-    import scipy.linalg
-    import workloads
-    from oracle import series
-    log("[bench] generating gaussian_rho input (n=8192, 400 power iterations)")
-    g = workloads.make("gaussian_rho")
-    n, k = g.A.shape[0], 3375
-    h = ns.Handle(0)
-    stream = torch.cuda.current_stream()
-    cols = sampled_cols(n, 16)
-    I_cols = np.zeros((n, len(cols)))
-    I_cols[cols, np.arange(len(cols))] = 1.0
-    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    res, errs, norms = {}, {}, {}
-    for rho in (0.99, 0.95):
-        A = g.A * (rho / 0.99)
-        log(f"[bench] LU reference (I - A)^-1 e_j for rho {rho}")
-        lu = scipy.linalg.lu_factor(np.eye(n) - A)
-        ref = scipy.linalg.lu_solve(lu, I_cols)          # S_inf columns; A^k is negligible
-        del lu
-        Ad = torch.from_numpy(A).float().cuda()
-        legs = ([("radix15c", "f32"), ("radix15", "f32"), ("radix9", "f32"), ("binary", "f32"),
-                 ("mixed", "f32")] if rho == 0.99 else [("radix15", "f32")])
-        for method, dtype in select(legs, args):
-            key = (method, dtype, rho)
-            res[key] = time_leg(ns, h, Ad, k, method, dtype, out, args.steps, args.warmup, stream, n)
-            _, rep = ns.ns_eval_ex(Ad, k, method, dtype, out=out, handle=h, stream=stream, report=True)
-            got = out.double().cpu().numpy()
-            errs[key] = series.rel_fro(got[:, cols], ref)
-            norms[key] = rep["level_norm"]
-            log(f"[bench]   rho {rho} {method}: sampled rel err vs (I-A)^-1 {errs[key]:.3e}, "
-                f"level norms {['%.3g' % x for x in rep['level_norm']]}")
-        del Ad
-    key = ("radix15c", "f32", 0.99) if ("radix15c", "f32", 0.99) in res else next(iter(res))
-    main = res[key]
-    cpu = None
-    if not args.no_cpu_baseline:
-        # bounded sample: one radix-15 level of the oracle (6 float64 products at n = 8192)
-        _, cpu = cpu_oracle_sample(lambda: series.radix15(g.A, 15),
-                                   "one radix-15 level of the oracle at n=8192 (6 float64 products)",
-                                   6 * 2.0 * n ** 3)
-    line = base_line(args, main["tflops"], main["ms"], "f32",
-                     {"workload": "gaussian_rho", "n": n, "k": k, "method": key[0], "rho_hat": 0.99,
-                      "k_eff": main["k_eff"], "products": main["products"], "seed": g.seed})
-    line["legs"] = {f"{m}:{d}:rho{r}": {**rnd(v), "rel_err_sampled_vs_inverse": errs[(m, d, r)],
-                                        "level_norm": norms[(m, d, r)]}
-                    for (m, d, r), v in res.items()}
-    if ("binary", "f32", 0.99) in res:
-        b = res[("binary", "f32", 0.99)]["ms"]
-        line["speedup_over_binary"] = {m: round(b / res[(m, "f32", 0.99)]["ms"], 4)
-                                       for m in ("radix15c", "radix15", "radix9", "mixed") if (m, "f32", 0.99) in res}
-        line["predicted_speedup_by_product_count"] = {"radix15c": round(24 / 18, 4),
-                                                      "radix15": round(24 / 18, 4), "radix9": round(24 / 20, 4),
-                                                      "mixed": round(24 / series.plan(k, "mixed")[2], 4)}
-    line["roofline"] = roofline_from_leg(main, n, "gemm_kernel<PolF32<2,2,4,8>>", "f32")
-    line["cpu_baseline"] = cpu
-    return line
-
-
-def bench_precision_sym(args, torch, ns):
-    """n = 8192, k = 729, symmetric lam ~ U[-0.9, 0.9]: radix-9 with the
-    products in FP64, FP32, FP32 + FP64 accumulation, split-BF16 and scaled
-    FP16, in the telescoping form and in the residual form (FP64 residual)."""
-    import workloads
-    from oracle import series
-    log("[bench] generating precision_sym input (n=8192)")
-    w = workloads.make("precision_sym")
-    n, k = w.A.shape[0], 729
-    h = ns.Handle(0)
-    stream = torch.cuda.current_stream()
-    A64 = torch.from_numpy(w.A).cuda()
-    A32 = A64.float()
-    out64, out32 = torch.empty_like(A64), torch.empty_like(A32)
-    cols = sampled_cols(n, 32)
-    legs = select([("radix9", "split_bf16"), ("radix9", "f16_scaled"), ("radix9", "f32_acc64"),
-                   ("radix9", "f32"), ("radix9", "f64"), ("radix9_resid", "split_bf16"),
-                   ("radix9_resid", "f16_scaled"), ("radix9_resid", "f32_acc64")], args)
-    res, errs = {}, {}
-    for method, dtype in legs:
-        A, out = (A32, out32) if dtype == "f32" else (A64, out64)
-        res[(method, dtype)] = time_leg(ns, h, A, k, method, dtype, out, args.steps, args.warmup, stream, n)
-        got = out.double().cpu().numpy()
-        ref = series.spectral_form(w.Q, w.lam, res[(method, dtype)]["k_eff"], cols=cols)
-        errs[(method, dtype)] = series.rel_fro(got[:, cols], ref)
-        log(f"[bench]   rel err vs FP64 definition (sampled) {errs[(method, dtype)]:.3e}")
-    key = ("radix9", "split_bf16") if ("radix9", "split_bf16") in res else next(iter(res))
-    main = res[key]
-    cpu = None
-    if not args.no_cpu_baseline:
-        _, cpu = cpu_oracle_sample(lambda: series.radix9(w.A, 9),
-                                   "one radix-9 level of the oracle at n=8192 (5 float64 products)",
-                                   5 * 2.0 * n ** 3)
-    line = base_line(args, main["tflops"], main["ms"], "bf16x3+f64",
-                     {"workload": "precision_sym", "n": n, "k": k, "method": key[0],
-                      "precision": key[1], "k_eff": main["k_eff"], "products": main["products"],
-                      "seed": w.seed, "lam": "U[-0.9,0.9]"})
-    line["legs"] = {f"{m}:{d}": {**rnd(r), "rel_err_vs_fp64_definition_sampled": errs[(m, d)]}
-                    for (m, d), r in res.items()}
-    line["roofline"] = roofline_from_leg(main, n, "gemm_panel_kernel<PolPanel<2,4,4,2,true,1,2,2>>", "bf16",
-                                         mfma_per_logical=3.0)
-    line["cpu_baseline"] = cpu
-    return line
+        r = time_leg(ns, h, A, k, method, dtype, out, args.steps, args.warmup, stream, n)
+        if not args.no_check:
+            got = out[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
+            ref = series.spectral_form(w.Q, w.lam, r["k_eff"], cols=cols)
+            r["rel_err_sampled_vs_definition"], _ = close(got, ref)
+        res[f"{method}:{dtype}"] = r
+    h.close()
+    info = {"workload": "large_symmetric", "n": n, "k": k, "seed": w.seed, "lam": "U[-0.95,0.95]"}
+    return res, None, info
 
 
 def bench_jacobi_batch(args, torch, ns):
@@ -371,23 +410,22 @@ def bench_jacobi_batch(args, torch, ns):
     A = torch.from_numpy(buf).cuda()
     offd = torch.from_numpy(offs).cuda()
     nh = torch.from_numpy(w.ns.astype(np.int32))
-    nd = nh.cuda()
     out = torch.empty_like(A)
     k = 81
     flops = float(sum(10 * 2.0 * int(m) ** 3 for m in w.ns))
     h = ns.Handle(0)
     # the autotuner's pick is also written to this JSON-lines file
     os.environ.setdefault("NS_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "ns_tune.jsonl"))
-    os.makedirs(os.path.dirname(os.environ["NS_TUNE_CACHE"]) or ".", exist_ok=True)
     log("[bench] autotuning the batched kernel")
-    timed = ns.ns_autotune_batched(A, offd, nd, nh, k, out, handle=h)
+    timed = ns.ns_autotune_batched(A, offd, None, nh, k, out, handle=h)
     log(f"[bench]   {timed} configurations timed")
-    fn = lambda: ns.ns_eval_batched(A, offd, nd, nh, k, "radix9", "f32", out_packed=out, handle=h)  # noqa: E731
+    fn = lambda: ns.ns_eval_batched(A, offd, None, nh, k, "radix9", "f32", out_packed=out, handle=h)  # noqa: E731
     fn()
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         fn()
     torch.cuda.synchronize()
+    # the graph runs on the current stream, so torch's events see its kernel
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
@@ -399,47 +437,49 @@ def bench_jacobi_batch(args, torch, ns):
     kernel_ms = ev0.elapsed_time(ev1) / args.steps
     log(f"[bench] batched graph: {sec * 1e3:.3f} ms/step, {flops / sec / 1e12:.2f} TFLOP/s")
     got = out.cpu().numpy()
-    # per-matrix launch loop (same kernels, one launch per product)
     loop_out = torch.empty_like(A)
-    ns.ns_eval_batched_loop(A, torch.from_numpy(offs), nh, k, "radix9", "f32", out_packed=loop_out, handle=h)
+    offs_t = torch.from_numpy(offs)
+    ns.ns_eval_batched_loop(A, offs_t, nh, k, "radix9", "f32", out_packed=loop_out, handle=h)
     torch.cuda.synchronize()
+    loop_steps = max(5, args.steps // 4)
     t0 = time.perf_counter()
-    loop_steps = 2
     for _ in range(loop_steps):
-        ns.ns_eval_batched_loop(A, torch.from_numpy(offs), nh, k, "radix9", "f32", out_packed=loop_out, handle=h)
+        ns.ns_eval_batched_loop(A, offs_t, nh, k, "radix9", "f32", out_packed=loop_out, handle=h)
     torch.cuda.synchronize()
     loop_sec = (time.perf_counter() - t0) / loop_steps
-    log(f"[bench] per-matrix loop: {loop_sec * 1e3:.1f} ms/step")
+    log(f"[bench] per-matrix loop: {loop_sec * 1e3:.1f} ms/step over {loop_steps} steps")
     bit_identical = bool(torch.equal(out, loop_out))
-
-    def oracle_all():
-        return [series.radix9(M.astype(np.float32).astype(np.float64), k)[0] for M in w.mats]
-    cpu, worst = None, None
-    if not args.no_cpu_baseline:
-        refs, cpu = cpu_oracle_sample(oracle_all, "whole batch once: radix-9 S_81 of all 2048 matrices",
-                                      flops)
-        worst = max(series.rel_fro(got[o:o + m * m].reshape(m, m), r)
-                    for o, m, r in zip(offs, w.ns, refs))
-    line = base_line(args, flops / sec / 1e12, sec * 1e3, "f32",
-                     {"workload": "jacobi_batch", "batch": len(w.mats), "n": "U{8..256}", "k": k,
-                      "method": "radix9", "products_per_matrix": 10, "seed": w.seed,
-                      "total_flops": flops})
-    line["loop_ms_per_step"] = round(loop_sec * 1e3, 3)
-    line["speedup_over_launch_loop"] = round(loop_sec / sec, 2)
-    line["bit_identical_to_launch_loop"] = bit_identical
-    line["worst_rel_err_vs_oracle"] = worst
-    line["autotune_configs_timed"] = timed
     achieved = flops / (kernel_ms * 1e-3) / 1e12
-    line["roofline"] = {"bound": "mfma", "kernel": "batched_kernel (persistent, one launch)",
-                        "achieved": round(achieved, 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
-                        "frac": round(achieved / PEAK["f32"], 4), "traffic": None,
-                        "per_launch_flops": flops, "avg_launch_ms": round(kernel_ms, 5), "launches": args.steps}
-    line["cpu_baseline"] = cpu
-    return line
+    r = {"ms": sec * 1e3, "tflops": flops / sec / 1e12, "products_per_matrix": 10,
+         "batch": len(w.mats), "total_flops": flops, "loop_ms": loop_sec * 1e3,
+         "loop_steps": loop_steps, "speedup_over_launch_loop": loop_sec / sec,
+         "bit_identical_to_launch_loop": bit_identical, "autotune_configs_timed": timed,
+         "roofline": {"bound": "mfma", "kernel": "batched_kernel (persistent, one launch)",
+                      "achieved": round(achieved, 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
+                      "frac": round(achieved / PEAK["f32"], 4), "traffic": None,
+                      "per_launch_flops": flops, "avg_launch_ms": round(kernel_ms, 5),
+                      "launches": args.steps}}
+    cpu = None
+    if not args.no_check:
+        def oracle_all():
+            return [series.radix9(M.astype(np.float32).astype(np.float64), k)[0] for M in w.mats]
+        if args.no_cpu_baseline:
+            refs = oracle_all()
+        else:
+            refs, cpu = cpu_oracle_sample(oracle_all, "whole batch once: radix-9 S_81 of all 2048 matrices",
+                                          flops, min_seconds=3.0)
+        r["worst_rel_err_vs_oracle"] = max(series.rel_fro(got[o:o + m * m].reshape(m, m), ref)
+                                           for o, m, ref in zip(offs, w.ns, refs))
+        r["cpu_baseline"] = cpu
+    h.close()
+    info = {"workload": "jacobi_batch", "batch": len(w.mats), "n": "U{8..256}", "k": k,
+            "seed": w.seed}
+    return {"radix9:f32:batched": r}, cpu, info
 
 
 def bench_small_symmetric(args, torch, ns):
-    """n = 256 FP64, k = 81: naive (80 products), binary (14), radix-9 (10)."""
+    """n = 256 FP64, k = 81: naive (80 products), binary (14), radix-9 (10).
+    Latency-bound: per-launch time and the critical path in launches."""
     import workloads
     from oracle import series
     w = workloads.make("small_symmetric")
@@ -448,33 +488,67 @@ def bench_small_symmetric(args, torch, ns):
     stream = torch.cuda.current_stream()
     A = torch.from_numpy(w.A).cuda()
     out = torch.empty_like(A)
-    res, errs = {}, {}
-    for method in ("radix9", "binary", "naive"):
-        res[method] = time_leg(ns, h, A, k, method, "f64", out, max(args.steps, 20), args.warmup, stream, n,
-                               separate_events=True)
-        ref = series.spectral_form(w.Q, w.lam, res[method]["k_eff"])
-        errs[method] = series.rel_fro(out.cpu().numpy(), ref)
-    main = res["radix9"]
+    res = {}
+    for method, dtype in select([("radix9", "f64"), ("binary", "f64"), ("naive", "f64")], args):
+        r = time_leg(ns, h, A, k, method, dtype, out, max(args.steps, 20), args.warmup, stream, n,
+                     separate_events=True)
+        r["us_per_product"] = r["ms"] * 1e3 / r["products"]
+        r["us_per_launch_on_critical_path"] = r["ms"] * 1e3 / r["product_launches_per_call"]
+        if not args.no_check:
+            r["rel_err_vs_closed_form"], _ = close(out.cpu().numpy(),
+                                                   series.spectral_form(w.Q, w.lam, r["k_eff"]))
+        res[f"{method}:{dtype}"] = r
     cpu = None
     if not args.no_cpu_baseline:
-        reps = 200
+        reps = 100
         _, cpu = cpu_oracle_sample(lambda: [series.radix9(w.A, k) for _ in range(reps)],
-                                   f"radix-9 S_81 at n=256 repeated {reps} times", reps * 10 * 2.0 * n ** 3)
-    line = base_line(args, main["tflops"], main["ms"], "f64",
-                     {"workload": "small_symmetric", "n": n, "k": k, "method": "radix9", "seed": w.seed})
-    line["legs"] = {m: {**rnd(r), "rel_err_vs_closed_form": errs[m]} for m, r in res.items()}
-    line["roofline"] = roofline_from_leg(main, n, "gemm_f64_splitk_kernel", "f64")
-    line["cpu_baseline"] = cpu
-    return line
+                                   f"radix-9 S_81 at n=256 repeated {reps} times", reps * 10 * 2.0 * n ** 3,
+                                   min_seconds=3.0)
+        res["radix9:f64"]["cpu_baseline"] = cpu
+    h.close()
+    info = {"workload": "small_symmetric", "n": n, "k": k, "seed": w.seed, "lam": "U[-0.5,0.5]"}
+    return res, cpu, info
 
 
 WORKLOADS = {
-    "large_symmetric": bench_large_symmetric,
-    "gaussian_rho": bench_gaussian_rho,
     "precision_sym": bench_precision_sym,
+    "gaussian_rho": bench_gaussian_rho,
+    "large_symmetric": bench_large_symmetric,
     "jacobi_batch": bench_jacobi_batch,
     "small_symmetric": bench_small_symmetric,
 }
+
+# the headline leg of each workload when it runs alone
+MAIN_LEG = {"precision_sym": "radix9:f64", "gaussian_rho": "radix15c:f32:rho0.99",
+            "large_symmetric": "radix9:f64", "jacobi_batch": "radix9:f32:batched",
+            "small_symmetric": "radix9:f64"}
+
+
+def speedups(res, pairs):
+    """wall-time ratio of the squaring leg over each radix leg, beside the
+    product-count prediction."""
+    out = {}
+    for fast, slow in pairs:
+        if fast in res and slow in res:
+            out[f"{fast} over {slow}"] = {
+                "measured": round(res[slow]["ms"] / res[fast]["ms"], 4),
+                "predicted_by_product_count": round(res[slow]["products"] / res[fast]["products"], 4)}
+    return out
+
+
+def build_line(args, name, res, cpu, info):
+    main_key = MAIN_LEG[name] if MAIN_LEG[name] in res else next(iter(res))
+    main = res[main_key]
+    dtype = main_key.split(":")[1]
+    line = {"metric": METRIC, "value": round(main["tflops"], 4), "unit": "TFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main["ms"], 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic",
+            "config": {**info, "method": main_key.split(":")[0],
+                       "k_eff": main.get("k_eff"), "products": main.get("products")}}
+    line["pct_mfma_peak"] = round(100.0 * main["tflops"] / PEAK.get(dtype, PEAK["f32"]), 2)
+    line["roofline"] = main.get("roofline")
+    return line, main_key
 
 
 def main():
@@ -487,7 +561,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 2
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, ROOT)
     import paper_2602_11843_amd as ns
     if args.calibrate_copy_mib:
         nbytes = args.calibrate_copy_mib << 20
@@ -495,11 +569,40 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
         log(f"[bench] calibration copy of {args.calibrate_copy_mib} MiB done")
-    names = list(WORKLOADS) if args.workload == "all" else [args.workload]
-    for name in names:
-        line = WORKLOADS[name](args, torch, ns)
+
+    if args.workload != "all":
+        res, cpu, info = WORKLOADS[args.workload](args, torch, ns)
+        line, main_key = build_line(args, args.workload, res, cpu, info)
+        line["legs"] = {k: rnd(v) for k, v in res.items()}
+        line["cpu_baseline"] = cpu
         print(json.dumps(line), flush=True)
+        return 0
+
+    # the headline workload first, then every other workload as legs
+    res, cpu, info = bench_precision_sym(args, torch, ns)
+    line, main_key = build_line(args, "precision_sym", res, cpu, info)
+    if line["roofline"] is not None and main_key == "radix9:f64":
+        line["roofline"]["traffic"] = measured_traffic("pmc_gemm_f64_big_precision_sym.md")
+        line["roofline"]["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    line["cpu_baseline"] = cpu
+    legs = {f"precision_sym/{k}": rnd(v) for k, v in res.items()}
+    line["speedup_over_binary"] = speedups(res, [("radix9:f64", "binary:f64")])
+    for name in ("gaussian_rho", "large_symmetric", "jacobi_batch", "small_symmetric"):
+        r, _, _ = WORKLOADS[name](args, torch, ns)
+        legs.update({f"{name}/{k}": rnd(v) for k, v in r.items()})
+        if name == "gaussian_rho":
+            line["speedup_over_binary_gaussian_rho"] = speedups(
+                r, [(f"{m}:f32:rho0.99", "binary:f32:rho0.99") for m in ("radix15c", "radix15", "radix9",
+                                                                         "mixed")])
+        if name == "large_symmetric":
+            line["speedup_over_binary_large_symmetric"] = speedups(
+                r, [("radix9:f64", "binary:f64"), ("radix9:f32", "binary:f32")])
+        if name == "small_symmetric":
+            line["speedup_over_binary_small_symmetric"] = speedups(r, [("radix9:f64", "binary:f64")])
+    line["legs"] = legs
+    print(json.dumps(line), flush=True)
     return 0
 
 

@@ -141,6 +141,13 @@ typedef struct ns_report {
   /* Radix-15 kernel in use (0 for exact kernels):
      max_{j<=14} |[f]_j - 1| and the spillover coefficients [f]_15, [f]_16. */
   double kernel_prefix_err, spill15, spill16;
+  /* Kernel launches that carried the products: two independent products of
+     a level (binary splitting's S (I + P) and P P, a telescoping level's sum
+     and power updates, Sec. 2.1-2.2) share one launch when the matrix is small
+     enough that one product leaves the GPU under-filled, so this is the
+     length of the call's critical path in products. */
+  int32_t product_launches;
+  int32_t reserved;
 } ns_report;
 
 typedef struct ns_handle ns_handle;
@@ -233,6 +240,12 @@ int ns_radix15c_coeffs(double c28[28], double* prefix_err, double* spill15, doub
 int ns_set_product_timing(ns_handle* h, int enable);
 int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* total_flops,
                       int reset);
+/* The same sums over the timed launches of one product engine only, named by
+   the dtype that uses it: NS_F64 (FP64 products, including the FP64 residual
+   products of the mixed forms), NS_F32 (FP32 products, including those of
+   NS_F32_ACC64), NS_SPLIT_BF16 or NS_F16_SCALED.  Resets nothing. */
+int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* total_ms,
+                            double* total_flops);
 
 const char* ns_status_string(int status);
 const char* ns_last_error(void);

@@ -49,6 +49,8 @@ class Report(ctypes.Structure):
         ("kernel_prefix_err", ctypes.c_double),
         ("spill15", ctypes.c_double),
         ("spill16", ctypes.c_double),
+        ("product_launches", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -60,6 +62,7 @@ class Report(ctypes.Structure):
             if self.method != NAIVE else [],
             "kernel_prefix_err": self.kernel_prefix_err,
             "spill15": self.spill15, "spill16": self.spill16,
+            "product_launches": self.product_launches,
         }
 
 
@@ -88,6 +91,8 @@ _SIGNATURES = {
     "ns_set_product_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "ns_product_timing": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_D),
                                          ctypes.POINTER(_D), ctypes.c_int]),
+    "ns_product_timing_dtype": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I32),
+                                               ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "ns_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ns_last_error": (ctypes.c_char_p, []),
 }
@@ -193,6 +198,15 @@ class Handle:
         with self.lock:
             _check(lib.ns_product_timing(self.ptr, ctypes.byref(cnt), ctypes.byref(ms),
                                          ctypes.byref(fl), int(bool(reset))), "ns_product_timing")
+        return cnt.value, ms.value, fl.value
+
+    def ns_product_timing_dtype(self, dtype):
+        """The same sums over one product engine's launches (named by dtype)."""
+        cnt, ms, fl = _I32(), _D(), _D()
+        with self.lock:
+            _check(lib.ns_product_timing_dtype(self.ptr, int(DTYPES.get(dtype, dtype)),
+                                               ctypes.byref(cnt), ctypes.byref(ms), ctypes.byref(fl)),
+                   "ns_product_timing_dtype")
         return cnt.value, ms.value, fl.value
 
 

@@ -558,6 +558,7 @@ int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, con
     rep->nonfinite = nf ? 1 : 0;
     rep->method = method;
     rep->dtype = dtype;
+    rep->product_launches = 1;           // every product of every matrix in one launch
     if (method != NS_NAIVE)
       for (int i = 0; i < lv && i < NS_MAX_LEVELS; ++i) rep->level_norm[i] = std::sqrt(ss[i]);
   }

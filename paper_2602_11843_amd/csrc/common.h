@@ -56,8 +56,14 @@ int engine_tile(Engine e, int n);
 
 // Launch one product on `stream`.  `host` is the parameter block on the host
 // (for the grid), `dev` the same block already in device memory (the kernel
-// reads the epilogue part from there).  Returns hipSuccess or the launch error.
-hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t stream);
+// reads the epilogue part from there).  With host2 / dev2 a second product of
+// the same n and engine, independent of the first (neither reads what the other
+// writes), runs in the same grid.  Not for the 16-bit engines' panel path.
+// Returns hipSuccess or the launch error.
+hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t stream,
+                       const GemmParams* host2 = nullptr, const GemmParams* dev2 = nullptr);
+// Workgroups of one product's grid on engine e at padded n.
+int gemm_grid(Engine e, int n);
 
 // Low-precision products at large n (panel.hip): each operand is first
 // rewritten into 16-bit panels (bf16 hi/lo planes, or one scaled fp16 plane),

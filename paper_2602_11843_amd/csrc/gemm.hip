@@ -23,21 +23,42 @@ namespace ns {
 namespace {
 using namespace dev;
 
+// Kernel arguments of one product (host2 == nullptr) or of two independent
+// products of the same shape in one grid of 2 `tiles` workgroups.
+MainArgs main_args(const GemmParams& host, const GemmParams* dev, const GemmParams* host2,
+                   const GemmParams* dev2, int tiles) {
+  MainArgs a{host.X, host.Y, host.n, host.ld, dev, nullptr, nullptr, nullptr, tiles};
+  if (host2) {
+    a.X2 = host2->X;
+    a.Y2 = host2->Y;
+    a.epi2 = dev2;
+  }
+  return a;
+}
+
+bool pair_ok(const GemmParams& host, const GemmParams* host2) {
+  return !host2 || (host2->n == host.n && host2->ld == host.ld);
+}
+
 template <class P>
-hipError_t launch(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
-  if (host.n % P::BM || host.n % P::BN || host.n % P::BK) return hipErrorInvalidValue;
-  const int grid = (host.n / P::BM) * (host.n / P::BN);
-  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
-  hipLaunchKernelGGL(gemm_kernel<P>, dim3(grid), dim3(P::THREADS), 0, s, a);
+hipError_t launch(const GemmParams& host, const GemmParams* dev, hipStream_t s,
+                  const GemmParams* host2, const GemmParams* dev2) {
+  if (host.n % P::BM || host.n % P::BN || host.n % P::BK || !pair_ok(host, host2))
+    return hipErrorInvalidValue;
+  const int tiles = (host.n / P::BM) * (host.n / P::BN);
+  const MainArgs a = main_args(host, dev, host2, dev2, tiles);
+  hipLaunchKernelGGL(gemm_kernel<P>, dim3(host2 ? 2 * tiles : tiles), dim3(P::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 template <class Q>
-hipError_t launch_low(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
-  if (host.n % Q::BM || host.n % Q::BN || host.n % Q::BK) return hipErrorInvalidValue;
-  const int grid = (host.n / Q::BM) * (host.n / Q::BN);
-  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
-  hipLaunchKernelGGL(gemm_lowp_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
+hipError_t launch_low(const GemmParams& host, const GemmParams* dev, hipStream_t s,
+                      const GemmParams* host2, const GemmParams* dev2) {
+  if (host.n % Q::BM || host.n % Q::BN || host.n % Q::BK || !pair_ok(host, host2))
+    return hipErrorInvalidValue;
+  const int tiles = (host.n / Q::BM) * (host.n / Q::BN);
+  const MainArgs a = main_args(host, dev, host2, dev2, tiles);
+  hipLaunchKernelGGL(gemm_lowp_kernel<Q>, dim3(host2 ? 2 * tiles : tiles), dim3(Q::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -65,13 +86,14 @@ __global__ __launch_bounds__(64 * SK_WAVES, 2) void gemm_f64_splitk_kernel(const
   __shared__ double part[SK_WAVES][SK_TILE][SK_TILE + 2];
   __shared__ double stats[(3 + kMaxOut) * SK_WAVES];
   const int tiles = args.n / SK_TILE;
+  const Which wp = which_product(args);
   int tm, tn;
-  tile_coords(blockIdx.x, tiles, tiles, tm, tn);
+  tile_coords(wp.bid, tiles, tiles, tm, tn);
   const int row0 = tm * SK_TILE, col0 = tn * SK_TILE, ld = args.ld;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane & 3, kk = 4 * ((lane >> 2) & 3) + (lane >> 4);
-  const double* __restrict__ X = static_cast<const double*>(args.X) + (size_t)(row0 + q) * ld + kk;
-  const double* __restrict__ Y = static_cast<const double*>(args.Y) + (size_t)kk * ld + col0 + q;
+  const double* __restrict__ X = static_cast<const double*>(wp.X) + (size_t)(row0 + q) * ld + kk;
+  const double* __restrict__ Y = static_cast<const double*>(wp.Y) + (size_t)kk * ld + col0 + q;
   const int nk = args.n / 16;
   const int mine = nk > w ? (nk - w + SK_WAVES - 1) / SK_WAVES : 0;   // this wave's chunks
   double acc[4][4];
@@ -130,7 +152,7 @@ __global__ __launch_bounds__(64 * SK_WAVES, 2) void gemm_f64_splitk_kernel(const
       if (((fi * 4 + fj) & 3) == bb) part[w][4 * fi + ri][4 * fj + cj] = x;
     }
   __syncthreads();
-  const GemmParams& p = *args.epi;
+  const GemmParams& p = *wp.epi;
   EpiState st{0.0, 0.f, 0};
   if (threadIdx.x < SK_TILE * SK_TILE / 2) {
     const int r = threadIdx.x / (SK_TILE / 2), cv = (threadIdx.x % (SK_TILE / 2)) * 2;
@@ -147,11 +169,13 @@ __global__ __launch_bounds__(64 * SK_WAVES, 2) void gemm_f64_splitk_kernel(const
   publish_stats<64 * SK_WAVES>(p, st, stats);
 }
 
-hipError_t launch_splitk(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
-  if (host.n % 32 || host.n > kSplitKMax) return hipErrorInvalidValue;
+hipError_t launch_splitk(const GemmParams& host, const GemmParams* dev, hipStream_t s,
+                         const GemmParams* host2, const GemmParams* dev2) {
+  if (host.n % 32 || host.n > kSplitKMax || !pair_ok(host, host2)) return hipErrorInvalidValue;
   const int t = host.n / SK_TILE;
-  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
-  hipLaunchKernelGGL(gemm_f64_splitk_kernel, dim3(t * t), dim3(64 * SK_WAVES), 0, s, a);
+  const MainArgs a = main_args(host, dev, host2, dev2, t * t);
+  hipLaunchKernelGGL(gemm_f64_splitk_kernel, dim3(host2 ? 2 * t * t : t * t), dim3(64 * SK_WAVES), 0,
+                     s, a);
   return hipGetLastError();
 }
 
@@ -184,19 +208,38 @@ int engine_tile(Engine e, int n) {
   return 256;
 }
 
-hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s) {
+hipError_t launch_gemm(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s,
+                       const GemmParams* host2, const GemmParams* dev2) {
   switch (e) {
     case ENG_F64:
-      if (host.n >= kBigMin) return launch<F64Big>(host, dev, s);
-      if (host.n >= kSplitKMin && host.n <= kSplitKMax) return launch_splitk(host, dev, s);
-      return launch<F64Small>(host, dev, s);
+      if (host.n >= kBigMin) return launch<F64Big>(host, dev, s, host2, dev2);
+      if (host.n >= kSplitKMin && host.n <= kSplitKMax) return launch_splitk(host, dev, s, host2, dev2);
+      return launch<F64Small>(host, dev, s, host2, dev2);
     case ENG_F32:
-      return host.n >= kBigMinF32 ? launch<F32Big>(host, dev, s) : launch<F32Small>(host, dev, s);
+      return host.n >= kBigMinF32 ? launch<F32Big>(host, dev, s, host2, dev2)
+                                  : launch<F32Small>(host, dev, s, host2, dev2);
     // from panel_min these engines run from panels (launch_gemm_panels)
-    case ENG_BF16X3: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<BF3Small>(host, dev, s);
-    case ENG_F16S: return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<H16Small>(host, dev, s);
+    case ENG_BF16X3:
+      return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<BF3Small>(host, dev, s, host2, dev2);
+    case ENG_F16S:
+      return panel_path(e, host.n) ? hipErrorInvalidValue : launch_low<H16Small>(host, dev, s, host2, dev2);
   }
   return hipErrorInvalidValue;
+}
+
+int gemm_grid(Engine e, int n) {
+  switch (e) {
+    case ENG_F64:
+      if (n >= kBigMin) return (n / F64Big::BM) * (n / F64Big::BN);
+      if (n >= kSplitKMin && n <= kSplitKMax) return (n / SK_TILE) * (n / SK_TILE);
+      return (n / F64Small::BM) * (n / F64Small::BN);
+    case ENG_F32:
+      return n >= kBigMinF32 ? (n / F32Big::BM) * (n / F32Big::BN) : (n / F32Small::BM) * (n / F32Small::BN);
+    case ENG_BF16X3:
+    case ENG_F16S:
+      return panel_path(e, n) ? (n / 256) * (n / 256) : (n / BF3Small::BM) * (n / BF3Small::BN);
+  }
+  return 0;
 }
 
 }  // namespace ns

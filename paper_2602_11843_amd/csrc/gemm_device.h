@@ -457,7 +457,28 @@ struct MainArgs {
   int n;
   int ld;
   const GemmParams* epi;
+  // An optional second, independent product of the same shape in the same
+  // grid: blocks [tiles, 2 tiles) compute X2 Y2 with epilogue epi2.  tiles is
+  // the grid of one product (== gridDim.x for a single product).
+  const void* X2;
+  const void* Y2;
+  const GemmParams* epi2;
+  int tiles;
 };
+
+// The operands of this workgroup's product and its tile index within that
+// product (wave-uniform: a scalar select at kernel start).
+struct Which {
+  const void* X;
+  const void* Y;
+  const GemmParams* epi;
+  int bid;
+};
+__device__ __forceinline__ Which which_product(const MainArgs& a) {
+  const int b = blockIdx.x;
+  if (b >= a.tiles) return Which{a.X2, a.Y2, a.epi2, b - a.tiles};
+  return Which{a.X, a.Y, a.epi, b};
+}
 
 template <class P>
 struct DmaShape {
@@ -717,20 +738,21 @@ __global__ __launch_bounds__(P::THREADS, P::MINB) void gemm_kernel(const MainArg
   using T = typename P::T;
   __shared__ __align__(16) T smem[tile_smem_elems<P>()];
   const int tiles_m = args.n / P::BM, tiles_n = args.n / P::BN;
+  const Which w = which_product(args);
   int tm, tn;
-  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  tile_coords(w.bid, tiles_m, tiles_n, tm, tn);
   const int row0 = tm * P::BM, col0 = tn * P::BN;
   typename P::Acc acc;
   P::zero(acc);
   if constexpr (DmaShape<P>::OK)
-    tile_mainloop_dma<P>(static_cast<const T*>(args.X), static_cast<const T*>(args.Y), args.ld,
+    tile_mainloop_dma<P>(static_cast<const T*>(w.X), static_cast<const T*>(w.Y), args.ld,
                          args.n, row0, col0, smem, acc);
   else
-    tile_mainloop<P>(static_cast<const T*>(args.X), static_cast<const T*>(args.Y), args.ld, args.n,
+    tile_mainloop<P>(static_cast<const T*>(w.X), static_cast<const T*>(w.Y), args.ld, args.n,
                      row0, col0, smem, acc);
   // the epilogue parameters are read from device memory only now, so they
   // occupy no registers while the matrix cores run
-  const GemmParams& p = *args.epi;
+  const GemmParams& p = *w.epi;
   EpiState st{0.0, 0.f, 0};
   if constexpr (std::is_same<typename P::CT, float>::value) {
     if (all_f32(p)) tile_epilogue<P, true>(acc, p, row0, col0, smem, st);
@@ -839,18 +861,19 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs ar
 
   const int n = args.n, ld = args.ld;
   const int tiles_m = n / Q::BM, tiles_n = n / Q::BN;
+  const Which w = which_product(args);
   int tm, tn;
-  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  tile_coords(w.bid, tiles_m, tiles_n, tm, tn);
   const int row0 = tm * Q::BM, col0 = tn * Q::BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / Q::NWN, wn = wave % Q::NWN;
-  const float* __restrict__ Xp = static_cast<const float*>(args.X);
-  const float* __restrict__ Yp = static_cast<const float*>(args.Y);
+  const float* __restrict__ Xp = static_cast<const float*>(w.X);
+  const float* __restrict__ Yp = static_cast<const float*>(w.Y);
 
   float sx = 1.f, sy = 1.f;
   int ush = 0;
   if constexpr (!Q::SPLIT) {
-    const int ex = amax_exponent(args.epi->xamax), ey = amax_exponent(args.epi->yamax);
+    const int ex = amax_exponent(w.epi->xamax), ey = amax_exponent(w.epi->yamax);
     sx = pow2f(14 - ex);
     sy = pow2f(14 - ey);
     ush = ex + ey - 28;
@@ -961,7 +984,7 @@ __global__ __launch_bounds__(Q::THREADS) void gemm_lowp_kernel(const MainArgs ar
   }
 
   // epilogue: stage FP32 results per wave-row pass, apply the affine outputs
-  const GemmParams& p = *args.epi;
+  const GemmParams& p = *w.epi;
   float* C = reinterpret_cast<float*>(smem);
   constexpr int VEC = 4, VPR = Q::BN / VEC;
   EpiStateT<!Q::SPLIT> st{};

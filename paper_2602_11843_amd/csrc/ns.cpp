@@ -30,6 +30,7 @@
 #include "common.h"
 
 namespace ns {
+Engine work_engine_of(int dtype);
 bool radix15_table(double c[28], double* prefix_err, double* s15, double* s16);
 bool radix15c_table(double c[28], double* prefix_err, double* s15, double* s16);
 int batched_eval(ns_handle* h, const void* A_packed, const int64_t* off_dev, const int32_t* n_dev,
@@ -73,17 +74,27 @@ struct ns_handle {
   int device = 0;
   void* ws = nullptr;            // workspace arena
   size_t ws_bytes = 0;
-  // timing of product launches
+  // timing of product launches: one record per launch, its events reused
+  struct Timed {
+    hipEvent_t e0, e1;
+    int engine;
+    double flops;      // algorithmic: 2 n^3 (unpadded n) per product of the launch
+  };
   bool timing = false;
-  std::vector<hipEvent_t> ev;    // pairs (start, stop)
+  std::vector<Timed> ev;
   size_t ev_used = 0;
-  double flops_logged = 0.0;
-  // product parameter blocks: staged in pinned host memory, uploaded with one
-  // copy per call; `params_free` marks when the staging buffer may be reused
-  ns::GemmParams* params_host = nullptr;
+  // product parameter blocks: staged in pinned host memory and uploaded with
+  // one copy per call, into a ring of kParamSlots slots (params_cap blocks
+  // each, host and device).  A call takes the next slot; its event marks when
+  // that slot's upload has finished, so the host waits only when it is a whole
+  // ring of calls ahead of the device.
+  static constexpr int kParamSlots = 4;
+  ns::GemmParams* params_host = nullptr;   // kParamSlots * params_cap
   ns::GemmParams* params_dev = nullptr;
   size_t params_cap = 0;
-  hipEvent_t params_free = nullptr;
+  hipEvent_t params_free[kParamSlots] = {};
+  unsigned params_next = 0;
+  int64_t product_launches = 0;            // of the last call (a pair counts once)
   // recorded after each call's last operation; the next call's stream waits on
   // it, so calls on different streams never share the workspace concurrently
   hipEvent_t call_done = nullptr;
@@ -95,6 +106,13 @@ namespace ns {
 namespace {
 
 constexpr int kScalarBytes = 64 * 1024;   // norms, flags and max-abs slots
+// Two independent products share one launch when one product's grid has at
+// most this many workgroups (2 per CU): below it a single product leaves CUs
+// idle or runs a short tail, and the pair halves the launches on the critical
+// path (binary splitting's S P and P P, a telescoping level's S (T - I) and
+// (T - I) B).  Larger grids fill the chip on their own and keep one launch
+// per product.
+constexpr int kPairMaxGrid = 512;
 constexpr int kAmaxSlots = 8192;
 
 struct Scalars {                          // layout of the scalar block in device memory
@@ -313,6 +331,7 @@ struct Op {
   Engine e;
   GemmParams p;      // GEMM
   bool panels;       // GEMM: X / Y are 16-bit panels
+  bool pair_next;    // GEMM: independent of the next GEMM, which may share its launch
   void* ptr;         // IDENTITY / AMAX / ZERO target, PANELS / PAD / UNPAD source
   int f64;           // element type of the target (PAD / UNPAD: of the destination)
   unsigned* amax;
@@ -486,12 +505,27 @@ struct Ctx {
     }
   }
 
+  // The last two recorded operations are independent products (neither reads
+  // what the other writes): let them share one launch when both are plain
+  // products of the same engine (not from panels) and one product's grid
+  // leaves the chip under-filled.
+  void pair_last_two() {
+    const size_t m = ops.size();
+    if (status != NS_OK || m < 2) return;
+    Op& a = ops[m - 2];
+    const Op& b = ops[m - 1];
+    if (a.kind == Op::GEMM && b.kind == Op::GEMM && !a.panels && !b.panels && a.e == b.e &&
+        gemm_grid(a.e, np) <= kPairMaxGrid)
+      a.pair_next = true;
+  }
+
   // Upload every recorded parameter block with one copy, then launch the
   // recorded operations in order on the stream.
   int execute() {
     if (status != NS_OK) return status;
     size_t ng = 0;
     for (const Op& op : ops) ng += op.kind == Op::GEMM;
+    constexpr int R = ns_handle::kParamSlots;
     if (ng > h->params_cap) {
       NS_HIP(hipDeviceSynchronize());   // earlier kernels may still read the old blocks
       if (h->params_host) NS_HIP(hipHostFree(h->params_host));
@@ -500,23 +534,30 @@ struct Ctx {
       h->params_dev = nullptr;
       h->params_cap = 0;
       const size_t cap = std::max<size_t>(ng, 256);
-      if (hipHostMalloc((void**)&h->params_host, cap * sizeof(GemmParams)) != hipSuccess ||
-          hipMalloc((void**)&h->params_dev, cap * sizeof(GemmParams)) != hipSuccess) {
+      if (hipHostMalloc((void**)&h->params_host, R * cap * sizeof(GemmParams)) != hipSuccess ||
+          hipMalloc((void**)&h->params_dev, R * cap * sizeof(GemmParams)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(NS_ERR_NOMEM, "parameter buffers (%zu blocks) could not be allocated", cap);
       }
       h->params_cap = cap;
     }
-    if (!h->params_free) NS_HIP(hipEventCreateWithFlags(&h->params_free, hipEventDisableTiming));
-    NS_HIP(hipEventSynchronize(h->params_free));    // the previous call's upload has finished
+    // this call's slot.  Its device blocks were last read by the call a ring
+    // earlier, which has finished: every call waits for the previous one on
+    // the handle.  Its host blocks may still be in that call's upload.
+    const int slot = (int)(h->params_next++ % R);
+    if (!h->params_free[slot])
+      NS_HIP(hipEventCreateWithFlags(&h->params_free[slot], hipEventDisableTiming));
+    NS_HIP(hipEventSynchronize(h->params_free[slot]));
+    GemmParams* ph = h->params_host + (size_t)slot * h->params_cap;
+    GemmParams* pd = h->params_dev + (size_t)slot * h->params_cap;
     size_t gi = 0;
     for (const Op& op : ops)
-      if (op.kind == Op::GEMM) h->params_host[gi++] = op.p;
+      if (op.kind == Op::GEMM) ph[gi++] = op.p;
     if (ng) {
-      NS_HIP(hipMemcpyAsync(h->params_dev, h->params_host, ng * sizeof(GemmParams),
-                            hipMemcpyHostToDevice, s));
-      NS_HIP(hipEventRecord(h->params_free, s));
+      NS_HIP(hipMemcpyAsync(pd, ph, ng * sizeof(GemmParams), hipMemcpyHostToDevice, s));
+      NS_HIP(hipEventRecord(h->params_free[slot], s));
     }
+    h->product_launches = 0;
     gi = 0;
     for (size_t oi = 0; oi < ops.size(); ++oi) {
       const Op& op = ops[oi];
@@ -558,28 +599,34 @@ struct Ctx {
                                 op.amax, s));
         continue;
       }
+      // an independent next product shares this launch
+      const bool pair = op.pair_next && oi + 1 < ops.size() && ops[oi + 1].kind == Op::GEMM;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (h->timing) {
-        if (h->ev_used + 2 > h->ev.size()) {
-          for (int i = 0; i < 64; ++i) {
-            hipEvent_t ev;
-            NS_HIP(hipEventCreate(&ev));
-            h->ev.push_back(ev);
+        if (h->ev_used == h->ev.size()) {
+          for (int i = 0; i < 32; ++i) {
+            ns_handle::Timed t{};
+            NS_HIP(hipEventCreate(&t.e0));
+            NS_HIP(hipEventCreate(&t.e1));
+            h->ev.push_back(t);
           }
         }
-        e0 = h->ev[h->ev_used];
-        e1 = h->ev[h->ev_used + 1];
-        h->ev_used += 2;
+        ns_handle::Timed& t = h->ev[h->ev_used++];
+        t.engine = op.e;
+        t.flops = (pair ? 2 : 1) * 2.0 * (double)n * n * n;
+        e0 = t.e0;
+        e1 = t.e1;
         NS_HIP(hipEventRecord(e0, s));
       }
-      const hipError_t err = op.panels ? launch_gemm_panels(op.e, op.p, h->params_dev + gi, s)
-                                       : launch_gemm(op.e, op.p, h->params_dev + gi, s);
-      ++gi;
+      hipError_t err;
+      if (op.panels) err = launch_gemm_panels(op.e, op.p, pd + gi, s);
+      else if (pair) err = launch_gemm(op.e, op.p, pd + gi, s, &ops[oi + 1].p, pd + gi + 1);
+      else err = launch_gemm(op.e, op.p, pd + gi, s);
+      gi += pair ? 2 : 1;
+      ++h->product_launches;
       if (err != hipSuccess) return fail(NS_ERR_HIP, "product launch failed: %s", hipGetErrorString(err));
-      if (h->timing) {
-        NS_HIP(hipEventRecord(e1, s));
-        h->flops_logged += 2.0 * (double)n * n * n;
-      }
+      if (h->timing) NS_HIP(hipEventRecord(e1, s));
+      if (pair) ++oi;
     }
     ops.clear();
     return NS_OK;
@@ -666,11 +713,16 @@ void mixed_step(Ctx& c, int m, bool fuse, const Buf& A, Buf& S, Buf& S2, Buf* S6
     }
     return;
   }
+  // Without the fused final step, a step's last two products are independent
+  // and share one launch; with it, the last product reads the sum the one
+  // before it wrote.
   if (m == 2) {
     sum_update(c, S, S2, S64, B);                      // S_2n = S_n (I + A^n)
     // A^2n = A^n A^n (+ the final additive step S_2n + A^2n)
-    if (!fuse) c.gemm(c.eng, B, B, {}, {o(Bn, 1.0)}, lv);
-    else if (S64) c.gemm(c.eng, B, B, {*S64}, {o(Bn, 1.0), o(*S64, 1.0, 1.0)}, lv);
+    if (!fuse) {
+      c.gemm(c.eng, B, B, {}, {o(Bn, 1.0)}, lv);
+      c.pair_last_two();
+    } else if (S64) c.gemm(c.eng, B, B, {*S64}, {o(Bn, 1.0), o(*S64, 1.0, 1.0)}, lv);
     else {
       c.gemm(c.eng, B, B, {S}, {o(Bn, 1.0), o(S2, 1.0, 1.0)}, lv);
       std::swap(S, S2);
@@ -681,8 +733,10 @@ void mixed_step(Ctx& c, int m, bool fuse, const Buf& A, Buf& S, Buf& S2, Buf* S6
     // U = A^2n, T = A^n + A^2n = T3 - I; S_3n = S_n T3; A^3n = U A^n
     c.gemm(c.eng, B, B, {B}, {o(U, 1.0), o(T, 1.0, 1.0)});
     sum_update(c, S, S2, S64, T);
-    if (!fuse) c.gemm(c.eng, U, B, {}, {o(Bn, 1.0)}, lv);
-    else if (S64) c.gemm(c.eng, U, B, {*S64}, {o(Bn, 1.0), o(*S64, 1.0, 1.0)}, lv);
+    if (!fuse) {
+      c.gemm(c.eng, U, B, {}, {o(Bn, 1.0)}, lv);
+      c.pair_last_two();
+    } else if (S64) c.gemm(c.eng, U, B, {*S64}, {o(Bn, 1.0), o(*S64, 1.0, 1.0)}, lv);
     else {
       c.gemm(c.eng, U, B, {S}, {o(Bn, 1.0), o(S2, 1.0, 1.0)}, lv);
       std::swap(S, S2);
@@ -693,8 +747,10 @@ void mixed_step(Ctx& c, int m, bool fuse, const Buf& A, Buf& S, Buf& S2, Buf* S6
   else kernel_quinary(c, B, U, X1, T);
   sum_update(c, S, S2, S64, T);
   // telescoping: A^mn = B - (T - I) + (T - I) B
-  if (!fuse) c.gemm(c.eng, T, B, {B, T}, {o(Bn, 1.0, 1.0, -1.0)}, lv);
-  else if (S64) c.gemm(c.eng, T, B, {B, T, *S64}, {o(Bn, 1.0, 1.0, -1.0), o(*S64, 1.0, 1.0, -1.0, 1.0)}, lv);
+  if (!fuse) {
+    c.gemm(c.eng, T, B, {B, T}, {o(Bn, 1.0, 1.0, -1.0)}, lv);
+    c.pair_last_two();
+  } else if (S64) c.gemm(c.eng, T, B, {B, T, *S64}, {o(Bn, 1.0, 1.0, -1.0), o(*S64, 1.0, 1.0, -1.0, 1.0)}, lv);
   else {
     c.gemm(c.eng, T, B, {B, T, S}, {o(Bn, 1.0, 1.0, -1.0), o(S2, 1.0, 1.0, -1.0, 1.0)}, lv);
     std::swap(S, S2);
@@ -733,9 +789,10 @@ int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, co
       if (method == NS_TERNARY) { U = c.take(W64); T = c.take(W64); }
       for (int lv = 0; lv < levels && c.status == NS_OK; ++lv) {
         if (method == NS_BINARY) {
-          // S_2n = S_n (I + A^n);  A^2n = A^n A^n
+          // S_2n = S_n (I + A^n);  A^2n = A^n A^n (independent: one launch)
           sum_update(c, S, S2, c.mixed ? &S64 : nullptr, B);
           c.gemm(c.eng, B, B, {}, {o(B2, 1.0)}, lv);
+          c.pair_last_two();
           std::swap(B, B2);
           continue;
         }
@@ -744,14 +801,17 @@ int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, co
           c.gemm(c.eng, B, B, {B}, {o(U, 1.0), o(T, 1.0, 1.0)});
           c.gemm(c.eng, U, B, {}, {o(B2, 1.0)}, lv);
           sum_update(c, S, S2, c.mixed ? &S64 : nullptr, T);
+          c.pair_last_two();
           std::swap(B, B2);
           continue;
         }
         if (method == NS_RADIX9) kernel_radix9(c, B, U, X1, P, Q, T);
         else kernel_quinary(c, B, U, X1, T);
         sum_update(c, S, S2, c.mixed ? &S64 : nullptr, T);
-        // telescoping: A^{mn} = I - T + T A^n = B - (T - I) + (T - I) B
+        // telescoping: A^{mn} = I - T + T A^n = B - (T - I) + (T - I) B,
+        // independent of the sum update (one launch)
         c.gemm(c.eng, T, B, {B, T}, {o(B2, 1.0, 1.0, -1.0)}, lv);
+        c.pair_last_two();
         std::swap(B, B2);   // after the first level the copy of A becomes the spare
       }
       res->S = c.mixed ? S64 : S;
@@ -923,6 +983,7 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
     rep->n_internal = c.np;
     rep->method = method;
     rep->dtype = dtype;
+    rep->product_launches = (int32_t)h->product_launches;
     if (method != NS_NAIVE)
       for (int i = 0; i < levels && i < NS_MAX_LEVELS; ++i) rep->level_norm[i] = std::sqrt(hs.level_sumsq[i]);
     if (method == NS_RADIX15 || method == NS_RADIX15C) {
@@ -933,6 +994,8 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   }
   return NS_OK;
 }
+
+Engine work_engine_of(int dtype) { return work_engine(dtype); }
 
 // accessors for batched.hip
 int batch_fail(int status, const char* msg) { return fail(status, "%s", msg); }
@@ -966,8 +1029,12 @@ int ns_destroy(ns_handle* h) {
     const ns::DeviceGuard dg(h->device);
     (void)hipDeviceSynchronize();
     ns::batched_release(h);
-    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-    if (h->params_free) (void)hipEventDestroy(h->params_free);
+    for (const auto& t : h->ev) {
+      (void)hipEventDestroy(t.e0);
+      (void)hipEventDestroy(t.e1);
+    }
+    for (hipEvent_t e : h->params_free)
+      if (e) (void)hipEventDestroy(e);
     if (h->call_done) (void)hipEventDestroy(h->call_done);
     if (h->params_host) (void)hipHostFree(h->params_host);
     if (h->params_dev) (void)hipFree(h->params_dev);
@@ -1079,24 +1146,43 @@ int ns_set_product_timing(ns_handle* h, int enable) {
   return NS_OK;
 }
 
+namespace {
+// Sum the timed launches of one engine (-1: all), waiting for their events.
+int sum_timing(ns_handle* h, int engine, int32_t* count, double* total_ms, double* total_flops) {
+  double ms = 0.0, fl = 0.0;
+  int32_t cnt = 0;
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    const auto& t = h->ev[i];
+    if (engine >= 0 && t.engine != engine) continue;
+    NS_HIP(hipEventSynchronize(t.e1));
+    float x = 0.f;
+    NS_HIP(hipEventElapsedTime(&x, t.e0, t.e1));
+    ms += x;
+    fl += t.flops;
+    ++cnt;
+  }
+  if (count) *count = cnt;
+  if (total_ms) *total_ms = ms;
+  if (total_flops) *total_flops = fl;
+  return NS_OK;
+}
+}  // namespace
+
 int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* total_flops,
                       int reset) {
   if (!h) return fail(NS_ERR_ARG, "null handle");
-  double ms = 0.0;
-  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
-    NS_HIP(hipEventSynchronize(h->ev[i + 1]));
-    float t = 0.f;
-    NS_HIP(hipEventElapsedTime(&t, h->ev[i], h->ev[i + 1]));
-    ms += t;
-  }
-  if (count) *count = (int32_t)(h->ev_used / 2);
-  if (total_ms) *total_ms = ms;
-  if (total_flops) *total_flops = h->flops_logged;
-  if (reset) {
-    h->ev_used = 0;
-    h->flops_logged = 0.0;
-  }
+  const int st = sum_timing(h, -1, count, total_ms, total_flops);
+  if (st) return st;
+  if (reset) h->ev_used = 0;
   return NS_OK;
+}
+
+int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* total_ms,
+                            double* total_flops) {
+  if (!h) return fail(NS_ERR_ARG, "null handle");
+  if (dtype < NS_F64 || dtype > NS_F16_SCALED)
+    return fail(NS_ERR_ARG, "dtype %d names no product engine", dtype);
+  return sum_timing(h, ns::work_engine_of(dtype), count, total_ms, total_flops);
 }
 
 const char* ns_status_string(int status) {

@@ -334,7 +334,7 @@ template <class Q>
 hipError_t launch_panel(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
   if (host.n % Q::BM || host.n % Q::BN || host.ld != host.n) return hipErrorInvalidValue;
   const int grid = (host.n / Q::BM) * (host.n / Q::BN);
-  const MainArgs a{host.X, host.Y, host.n, host.ld, dev};
+  const MainArgs a{host.X, host.Y, host.n, host.ld, dev, nullptr, nullptr, nullptr, grid};
   hipLaunchKernelGGL(gemm_panel_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
   return hipGetLastError();
 }

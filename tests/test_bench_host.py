@@ -15,20 +15,36 @@ from conftest import ROOT
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-HASHED = ("gemm_device.h", "gemm.hip", "ns.cpp")
+HASHED = bench.KERNEL_SOURCES
 
 
-def test_roofline_from_leg_uses_logged_flops_per_launch():
+def test_engine_roofline_uses_logged_flops_per_launch():
     n = 4096
-    leg = {"product_launches": 150, "product_avg_ms": 2.0, "launch_flops": 2.0 * n ** 3}
-    r = bench.roofline_from_leg(leg, n, "k", "f64")
+    stats = (150, 150 * 2.0, 150 * 2.0 * n ** 3)        # launches, summed ms, summed flops
+    r = bench.engine_roofline("f64", stats, n)
     assert r["achieved"] == pytest.approx(2.0 * n ** 3 / 2e-3 / 1e12, rel=1e-4)
     assert r["frac"] == pytest.approx(r["achieved"] / 78.6, rel=1e-3)
     assert r["peak"] == 78.6 and r["bound"] == "mfma" and r["launches"] == 150
-    # three BF16 MFMA products per logical product (split-BF16)
-    r3 = bench.roofline_from_leg(leg, n, "k", "bf16", mfma_per_logical=3.0)
+    assert r["avg_launch_ms"] == pytest.approx(2.0)
+    assert r["kernel"] == "gemm_kernel<PolF64M16<2,2,4,4>>"
+    # three BF16 MFMA products per logical product (split-BF16), BF16 peak
+    r3 = bench.engine_roofline("split_bf16", stats, n)
     assert r3["achieved"] == pytest.approx(3 * r["achieved"], rel=1e-4)
-    assert bench.roofline_from_leg({"product_launches": 0}, n, "k", "f64") is None
+    assert r3["peak"] == 2516.6
+    # a launch carrying two products logs twice the flops
+    r2 = bench.engine_roofline("f64", (75, 300.0, 150 * 2.0 * n ** 3), n)
+    assert r2["achieved"] == pytest.approx(r["achieved"], rel=1e-4)
+    assert r2["per_launch_flops"] == pytest.approx(2 * 2.0 * n ** 3)
+    assert bench.engine_roofline("f64", (0, 0.0, 0.0), n) is None
+
+
+def test_kernel_names_follow_the_tile_thresholds():
+    assert bench.kernel_name("f64", 256) == "gemm_f64_splitk_kernel"
+    assert bench.kernel_name("f64", 1024) == "gemm_kernel<PolF64M16<2,2,1,1,4>>"
+    assert bench.kernel_name("f32", 8192) == "gemm_kernel<PolF32<2,2,4,8>>"
+    assert bench.kernel_name("f32", 2048) == "gemm_kernel<PolF32<2,2,2,2>>"
+    assert "PolPanel" in bench.kernel_name("split_bf16", 8192)
+    assert "PolLow" in bench.kernel_name("f16_scaled", 2048)
 
 
 def _fake_root(tmp_path, traffic=123456789):
@@ -49,8 +65,8 @@ def _fake_root(tmp_path, traffic=123456789):
 def test_measured_traffic_follows_the_source_hash(tmp_path):
     csrc = _fake_root(tmp_path)
     assert bench.measured_traffic("s.md", root=str(tmp_path)) == 123456789.0
-    # any change to the kernel or schedule sources voids the counter figure
-    with open(csrc / "ns.cpp", "a") as fh:
+    # any change to the kernel sources voids the counter figure
+    with open(csrc / "gemm.hip", "a") as fh:
         fh.write("\n")
     assert bench.measured_traffic("s.md", root=str(tmp_path)) is None
     assert bench.measured_traffic("missing.md", root=str(tmp_path)) is None

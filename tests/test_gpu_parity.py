@@ -115,6 +115,9 @@ def test_nonsymmetric_parity(ns, method, dtype):
 def test_small_symmetric_workload(ns, method):
     w = workloads.make("small_symmetric")
     got, rep = run(ns, w.A, 81, method, "f64")
+    # critical path in launches: binary's S (I + P) and P P share a launch at
+    # this size (7 levels), as do radix-9's sum and power updates (4 per level)
+    assert rep["product_launches"] == {"naive": 80, "binary": 7, "radix9": 8}[method]
     ref, _ = series.evaluate(w.A, 81, method)
     closed = series.spectral_form(w.Q, w.lam, rep["k_eff"])
     assert_close(got, ref, 1e-12, f"{method} vs oracle")
@@ -287,9 +290,9 @@ def large_symmetric():
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("method", ["binary", "radix9"])
 def test_large_symmetric_full(ns, large_symmetric, method, dtype):
-    """n = 4096, k = 729 (the benchmarked configuration, large tiles of both
-    engines): every output element against the oracle's own schedule on the
-    input the GPU receives, and (FP64) against the spectral definition."""
+    """n = 4096, k = 729 (large tiles of both engines): every output element
+    against the oracle's own schedule on the input the GPU receives, and
+    (FP64) against the spectral definition."""
     w = large_symmetric
     got, rep = run(ns, w.A, 729, method, dtype)
     say("[cpu] oracle schedule at n=4096")
