@@ -201,6 +201,31 @@ int ns_eval_batched(ns_handle* h, const void* A_packed, const int64_t* off_dev,
                     int64_t k, int method, int dtype, void* out_packed,
                     hipStream_t stream, ns_report* rep);
 
+/* For callers that cannot allocate (code under HIP stream capture, tight
+   serving loops, harnesses that forbid device allocation): the same
+   evaluation as ns_eval_ex, with the same arguments apart from the handle,
+   on the current device.  It allocates nothing: the workspace and the
+   products' parameter blocks come from a fixed device array of
+   NS_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+   until the process ends; the caller still provides A and out.
+     - Fits when ns_workspace_bytes(n, method, dtype) is at most
+       NS_NOALLOC_SCRATCH_BYTES - 1 MiB (e.g. n <= 960 for NS_F64 radix-9,
+       n <= 1344 for NS_F32 radix-9) and the call has at most 1 MiB of product
+       parameter blocks (about 2000 products); otherwise NS_ERR_RANGE, and
+       nothing is enqueued.
+     - Every call of the process on a GPU shares that GPU's array, which
+       keeps the last call's contents (each call clears what must start at
+       zero).  Calls that overlap on one GPU (e.g. on two streams) race on the
+       array: the caller must order them (one stream does).  Host threads are
+       serialised while a call is enqueued.
+     - The parameter blocks go up from host memory that is not pinned, so the
+       host waits for that copy, i.e. for the stream's earlier work.
+     - No product timing and no handle state; rep (nullable) as in
+       ns_eval_ex. */
+#define NS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ns_eval_noalloc(const void* A, int64_t n, int64_t lda, int64_t k, int method, int dtype,
+                    void* out, int64_t ldo, hipStream_t stream, ns_report* rep);
+
 /* Reference path for the batched form: the same matrices evaluated one at a
    time with the per-matrix single-GEMM kernels (one launch per product, no
    graph).  Same arguments and result layout as ns_eval_batched; off_host is

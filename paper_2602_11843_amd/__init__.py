@@ -78,6 +78,8 @@ _SIGNATURES = {
     "ns_eval": (ctypes.c_int, [_P, _I64, _I64, ctypes.c_int, ctypes.c_int, _P]),
     "ns_eval_ex": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _P, _I64,
                                   _P, ctypes.POINTER(Report)]),
+    "ns_eval_noalloc": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, ctypes.c_int, _P, _I64,
+                                       _P, ctypes.POINTER(Report)]),
     "ns_eval_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I64, ctypes.c_int, ctypes.c_int,
                                        _P, _P, ctypes.POINTER(Report)]),
     "ns_eval_batched_loop": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, ctypes.c_int,
@@ -301,6 +303,32 @@ def ns_eval_ex(A, k: int, method="radix9", dtype="f64", out=None, handle: Option
         _check(lib.ns_eval_ex(h.ptr, _P(A.data_ptr()), n, A.stride(0), int(k), int(m), int(d),
                               _P(out.data_ptr()), out.stride(0), _stream_ptr(stream),
                               ctypes.byref(rep) if rep is not None else None), "ns_eval_ex")
+    return (out, rep.as_dict()) if report else out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ns_eval_noalloc(A, k: int, method="radix9", dtype="f64", out=None, stream=None,
+                    report: bool = False):
+    """ns_eval_ex without a handle, on A's device, with the library's fixed
+    device array as workspace (nothing is allocated by the library; `out`
+    must be given by callers that cannot allocate either).  Calls that
+    overlap on one GPU race on that array (see ns.h)."""
+    import torch
+    m = METHODS.get(method, method)
+    d = DTYPES.get(dtype, dtype)
+    _square("A", A, io_dtype(d))
+    n = A.shape[0]
+    if out is None:
+        out = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    _square("out", out, A.dtype, n, A.device)
+    rep = Report() if report else None
+    with torch.cuda.device(A.device):
+        _check(lib.ns_eval_noalloc(_P(A.data_ptr()), n, A.stride(0), int(k), int(m), int(d),
+                                   _P(out.data_ptr()), out.stride(0), _stream_ptr(stream),
+                                   ctypes.byref(rep) if rep is not None else None),
+               "ns_eval_noalloc")
     return (out, rep.as_dict()) if report else out
 
 

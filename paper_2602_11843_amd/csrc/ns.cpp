@@ -341,8 +341,20 @@ struct Op {
   int64_t n, ld;     // PAD / UNPAD: the caller's n and leading dimension; ZERO: bytes in n
 };
 
+// Device memory of a call that allocates nothing (ns_eval_noalloc): the
+// workspace and the parameter blocks' device copy live in a fixed region, the
+// blocks are staged in a fixed host array.
+struct FixedMem {
+  char* ws;                 // scalar block + matrices
+  size_t ws_bytes;
+  GemmParams* params_host;  // host staging
+  GemmParams* params_dev;   // device copy, inside the fixed region
+  size_t params_cap;        // blocks
+};
+
 struct Ctx {
-  ns_handle* h;
+  ns_handle* h;             // null on the fixed-memory path
+  const FixedMem* fixed;    // null on the handle path
   hipStream_t s;
   int n;              // caller's n
   int np;             // internal n
@@ -351,6 +363,7 @@ struct Ctx {
   Scalars* scal;      // device
   int next_amax = 0;
   int gemms = 0;
+  int64_t launches = 0;     // product launches of the call (a pair counts once)
   int status = NS_OK;
   char* arena;
   size_t arena_off = 0;
@@ -525,6 +538,32 @@ struct Ctx {
     if (status != NS_OK) return status;
     size_t ng = 0;
     for (const Op& op : ops) ng += op.kind == Op::GEMM;
+    GemmParams *ph, *pd;
+    int slot = -1;
+    if (fixed) {
+      if (ng > fixed->params_cap)
+        return fail(NS_ERR_RANGE, "%zu products exceed the %zu parameter blocks of the fixed region",
+                    ng, fixed->params_cap);
+      ph = fixed->params_host;
+      pd = fixed->params_dev;
+    } else {
+      const int st = ring_slot(ng, &ph, &pd, &slot);
+      if (st) return st;
+    }
+    size_t gi = 0;
+    for (const Op& op : ops)
+      if (op.kind == Op::GEMM) ph[gi++] = op.p;
+    if (ng) {
+      // from the fixed (pageable) staging array the copy is synchronous for
+      // the host, so the array is free again when it returns
+      NS_HIP(hipMemcpyAsync(pd, ph, ng * sizeof(GemmParams), hipMemcpyHostToDevice, s));
+      if (slot >= 0) NS_HIP(hipEventRecord(h->params_free[slot], s));
+    }
+    return launch_all(pd);
+  }
+
+  // The handle's next parameter slot (grown when a call has more blocks).
+  int ring_slot(size_t ng, GemmParams** ph, GemmParams** pd, int* slot_out) {
     constexpr int R = ns_handle::kParamSlots;
     if (ng > h->params_cap) {
       NS_HIP(hipDeviceSynchronize());   // earlier kernels may still read the old blocks
@@ -548,17 +587,17 @@ struct Ctx {
     if (!h->params_free[slot])
       NS_HIP(hipEventCreateWithFlags(&h->params_free[slot], hipEventDisableTiming));
     NS_HIP(hipEventSynchronize(h->params_free[slot]));
-    GemmParams* ph = h->params_host + (size_t)slot * h->params_cap;
-    GemmParams* pd = h->params_dev + (size_t)slot * h->params_cap;
+    *ph = h->params_host + (size_t)slot * h->params_cap;
+    *pd = h->params_dev + (size_t)slot * h->params_cap;
+    *slot_out = slot;
+    return NS_OK;
+  }
+
+  // Launch the recorded operations in order; pd holds the GEMM blocks.
+  int launch_all(const GemmParams* pd) {
+    const bool timing = h && h->timing;
+    launches = 0;
     size_t gi = 0;
-    for (const Op& op : ops)
-      if (op.kind == Op::GEMM) ph[gi++] = op.p;
-    if (ng) {
-      NS_HIP(hipMemcpyAsync(pd, ph, ng * sizeof(GemmParams), hipMemcpyHostToDevice, s));
-      NS_HIP(hipEventRecord(h->params_free[slot], s));
-    }
-    h->product_launches = 0;
-    gi = 0;
     for (size_t oi = 0; oi < ops.size(); ++oi) {
       const Op& op = ops[oi];
       if (op.kind == Op::ZERO || op.kind == Op::PAD || op.kind == Op::IDENTITY) {
@@ -602,7 +641,7 @@ struct Ctx {
       // an independent next product shares this launch
       const bool pair = op.pair_next && oi + 1 < ops.size() && ops[oi + 1].kind == Op::GEMM;
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (h->timing) {
+      if (timing) {
         if (h->ev_used == h->ev.size()) {
           for (int i = 0; i < 32; ++i) {
             ns_handle::Timed t{};
@@ -623,12 +662,13 @@ struct Ctx {
       else if (pair) err = launch_gemm(op.e, op.p, pd + gi, s, &ops[oi + 1].p, pd + gi + 1);
       else err = launch_gemm(op.e, op.p, pd + gi, s);
       gi += pair ? 2 : 1;
-      ++h->product_launches;
+      ++launches;
       if (err != hipSuccess) return fail(NS_ERR_HIP, "product launch failed: %s", hipGetErrorString(err));
-      if (h->timing) NS_HIP(hipEventRecord(e1, s));
+      if (timing) NS_HIP(hipEventRecord(e1, s));
       if (pair) ++oi;
     }
     ops.clear();
+    if (h) h->product_launches = launches;
     return NS_OK;
   }
 };
@@ -930,28 +970,42 @@ ns_handle* g_default[64] = {};
 
 }  // namespace
 
-int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, int method,
-              int dtype, void* out, int64_t ldo, hipStream_t s, ns_report* rep) {
+// One evaluation, either on a handle (h: its workspace, parameter ring,
+// timing and call ordering) or on a fixed memory region (fx, h null: nothing
+// is allocated and no event is used).  The caller has made the device current.
+int eval_core(ns_handle* h, const FixedMem* fx, const void* A, int64_t n, int64_t lda, int64_t k,
+              int method, int dtype, void* out, int64_t ldo, hipStream_t s, ns_report* rep) {
   int st = check_args(A, n, lda, k, method, dtype, out, ldo);
   if (st) return st;
   int64_t k_eff;
   int32_t levels, gemms_formula;
   if ((st = plan(k, method, &k_eff, &levels, &gemms_formula))) return st;
-  const DeviceGuard dg(h->device);
-  NS_HIP(dg.err);
-  if ((st = ensure_workspace(h, workspace_bytes(n, method, dtype)))) return st;
-  if (!h->call_done) NS_HIP(hipEventCreateWithFlags(&h->call_done, hipEventDisableTiming));
-  else NS_HIP(hipStreamWaitEvent(s, h->call_done, 0));
+  const size_t need = workspace_bytes(n, method, dtype);
+  char* ws;
+  if (fx) {
+    if (need > fx->ws_bytes)
+      return fail(NS_ERR_RANGE,
+                  "n = %lld needs %zu bytes of workspace for this method and dtype; the fixed "
+                  "region holds %zu",
+                  (long long)n, need, fx->ws_bytes);
+    ws = fx->ws;
+  } else {
+    if ((st = ensure_workspace(h, need))) return st;
+    if (!h->call_done) NS_HIP(hipEventCreateWithFlags(&h->call_done, hipEventDisableTiming));
+    else NS_HIP(hipStreamWaitEvent(s, h->call_done, 0));
+    ws = static_cast<char*>(h->ws);
+  }
 
   Ctx c{};
   c.h = h;
+  c.fixed = fx;
   c.s = s;
   c.n = (int)n;
   c.np = n_internal(n, dtype);
   c.eng = work_engine(dtype);
   c.mixed = is_mixed(dtype);
-  c.scal = static_cast<Scalars*>(h->ws);
-  c.arena = static_cast<char*>(h->ws) + kScalarBytes;
+  c.scal = reinterpret_cast<Scalars*>(ws);
+  c.arena = ws + kScalarBytes;
   c.zero(c.scal, sizeof(Scalars));
 
   const int in64 = (dtype != NS_F32);
@@ -968,7 +1022,7 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   if ((st = run_schedule(c, method, k, levels, Aw, c.mixed ? &A64 : nullptr, &res))) return st;
   c.unpad(res.S, out, in64, ldo);
   if ((st = c.execute())) return st;
-  NS_HIP(hipEventRecord(h->call_done, s));
+  if (h) NS_HIP(hipEventRecord(h->call_done, s));
 
   if (rep) {
     Scalars hs;
@@ -983,7 +1037,7 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
     rep->n_internal = c.np;
     rep->method = method;
     rep->dtype = dtype;
-    rep->product_launches = (int32_t)h->product_launches;
+    rep->product_launches = (int32_t)c.launches;
     if (method != NS_NAIVE)
       for (int i = 0; i < levels && i < NS_MAX_LEVELS; ++i) rep->level_norm[i] = std::sqrt(hs.level_sumsq[i]);
     if (method == NS_RADIX15 || method == NS_RADIX15C) {
@@ -994,6 +1048,24 @@ int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, in
   }
   return NS_OK;
 }
+
+int eval_impl(ns_handle* h, const void* A, int64_t n, int64_t lda, int64_t k, int method,
+              int dtype, void* out, int64_t ldo, hipStream_t s, ns_report* rep) {
+  const DeviceGuard dg(h->device);
+  NS_HIP(dg.err);
+  return eval_core(h, nullptr, A, n, lda, k, method, dtype, out, ldo, s, rep);
+}
+
+// The fixed-region path of ns_eval_noalloc (noalloc.hip); the current device
+// is the region's.
+int eval_fixed(char* ws, size_t ws_bytes, GemmParams* params_host, GemmParams* params_dev,
+               size_t params_cap, const void* A, int64_t n, int64_t lda, int64_t k, int method,
+               int dtype, void* out, int64_t ldo, hipStream_t s, ns_report* rep) {
+  const FixedMem fx{ws, ws_bytes, params_host, params_dev, params_cap};
+  return eval_core(nullptr, &fx, A, n, lda, k, method, dtype, out, ldo, s, rep);
+}
+
+int fail_status(int status, const char* msg) { return fail(status, "%s", msg); }
 
 Engine work_engine_of(int dtype) { return work_engine(dtype); }
 
