@@ -17,7 +17,8 @@ the legs of the other workloads:
 
   precision_sym   radix-9 in FP32, FP32 + FP64 sum, split-BF16, scaled FP16;
                   the residual forms (FP64 residual) in split-BF16, scaled
-                  FP16 and FP32
+                  FP16 and FP32; split-BF16 with the residual exact only at
+                  the last two levels, or emulated from int8 slices
   gaussian_rho    n = 8192 FP32, nonsymmetric, rho_hat = 0.99, k = 3375:
                   radix-15 (contraction-aware table and App. B table),
                   radix-9 (k_eff 6561), binary (k_eff 4096), the exact any-k
@@ -47,10 +48,22 @@ import time
 import numpy as np
 
 METRIC = "S_k(A) time + GEMM TFLOP/s (%MFMA peak), radix-9/15 vs squaring at stated err"
-PEAK = {"f64": 78.6, "f32": 157.3, "split_bf16": 2516.6, "f16_scaled": 2516.6}   # dense, MI355X
-# MFMA work per logical product on each engine (split-BF16: three BF16 products)
+# dense MI355X peaks (TFLOP/s; int8: TOP/s)
+PEAK = {"f64": 78.6, "f32": 157.3, "split_bf16": 2516.6, "f16_scaled": 2516.6, "i8": 5000.0}
+# MFMA work per logical product on each engine (split-BF16: three BF16 products;
+# the int8-emulated residual: s (s + 1) / 2 int8 products, set per leg)
 MFMA_PER_LOGICAL = {"f64": 1.0, "f32": 1.0, "split_bf16": 3.0, "f16_scaled": 1.0}
-ENGINES = ("f64", "f32", "split_bf16", "f16_scaled")
+ENGINES = ("f64", "f32", "split_bf16", "f16_scaled", "i8")
+
+
+def resid_slices(dtype):
+    """int8 slices of a dtype name's residual modifier (0 without one)."""
+    for m in dtype.split("+")[1:]:
+        if m == "i8":
+            return 7
+        if m.startswith("i8x"):
+            return int(m[3:])
+    return 0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -94,22 +107,26 @@ def kernel_name(engine, n):
     if engine == "split_bf16":
         return ("gemm_panel_kernel<PolPanel<2,4,4,2,true,1,2,2>>" if n >= 3072
                 else "gemm_lowp_kernel<PolLow<2,2,1,1,true>>")
+    if engine == "i8":
+        return "gemm_i8_kernel<PolI8> (one launch per slice diagonal)"
     return ("gemm_panel_kernel<PolPanel<2,4,4,2,false,1,2,2>>" if n >= 2560
             else "gemm_lowp_kernel<PolLow<2,2,1,1,false>>")
 
 
-def engine_roofline(engine, stats, n):
+def engine_roofline(engine, stats, n, slices=0):
     """Roofline of one engine's product launches: MFMA work per launch (2 n^3
-    per logical product, times 3 for split-BF16) over the launches' average
-    duration, against that engine's dense MFMA peak."""
+    per logical product, times 3 for split-BF16, times s (s + 1) / 2 int8
+    products for the emulated residual) over the launches' average duration,
+    against that engine's dense MFMA peak."""
     cnt, ms, flops = stats
     if not cnt or ms <= 0:
         return None
-    mfma = MFMA_PER_LOGICAL[engine]
+    mfma = slices * (slices + 1) / 2 if engine == "i8" else MFMA_PER_LOGICAL[engine]
     achieved = mfma * flops / (ms * 1e-3) / 1e12
     peak = PEAK[engine]
     return {"bound": "mfma", "kernel": kernel_name(engine, n), "achieved": round(achieved, 3),
-            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "peak": peak, "unit": "TOP/s" if engine == "i8" else "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
             "per_launch_flops": mfma * flops / cnt, "avg_launch_ms": round(ms / cnt, 5),
             "launches": cnt}
 
@@ -177,12 +194,13 @@ def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate
         for _ in range(steps):
             fn()
         torch.cuda.synchronize()
-    per_engine = {e: h.ns_product_timing_dtype(e) for e in ENGINES}
+    per_engine = {e: h.ns_product_timing_dtype(ns.RESID_INT8(0) if e == "i8" else e) for e in ENGINES}
     cnt, kms, kfl = h.ns_product_timing(reset=True)
     h.ns_set_product_timing(False)
     _, rep = ns.ns_eval_ex(A, k, method, dtype, out=out, handle=h, stream=stream, report=True)
     flops = products * 2.0 * n ** 3
-    rooflines = {e: engine_roofline(e, st, rep["n_internal"]) for e, st in per_engine.items() if st[0]}
+    rooflines = {e: engine_roofline(e, st, rep["n_internal"], resid_slices(dtype))
+                 for e, st in per_engine.items() if st[0]}
     dominant = max(rooflines, key=lambda e: per_engine[e][1]) if rooflines else None
     r = {"ms": sec * 1e3, "tflops": flops / sec / 1e12, "products": products, "k_eff": k_eff,
          "levels": levels, "product_launches_per_call": rep["product_launches"],
@@ -291,7 +309,12 @@ def bench_precision_sym(args, torch, ns):
     legs = select([("radix9", "f64"), ("binary", "f64"), ("radix9", "f32"), ("radix9", "f32_acc64"),
                    ("radix9", "split_bf16"), ("radix9", "f16_scaled"),
                    ("radix9_resid", "split_bf16"), ("radix9_resid", "f16_scaled"),
-                   ("radix9_resid", "f32_acc64")], args)
+                   ("radix9_resid", "f32_acc64"),
+                   # the residual product exact only at the last two levels, or
+                   # emulated from int8 slices (s = 7, 6)
+                   ("radix9_resid", "split_bf16+last"), ("radix9_resid", "split_bf16+i8"),
+                   ("radix9_resid", "split_bf16+i8x6"), ("radix9_resid", "split_bf16+i8+last")],
+                  args)
     res = {}
     for method, dtype in legs:
         A, out = (A32, out32) if dtype == "f32" else (A64, out64)

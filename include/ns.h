@@ -110,6 +110,29 @@ enum ns_dtype {
   NS_F32_ACC64 = 4
 };
 
+/* Residual-product modifiers, OR-ed into the dtype of a residual method
+   (NS_RADIX15, NS_RADIX15C, NS_RADIX9_RESID, NS_HENSEL) in one of the
+   FP64-accumulating forms (NS_SPLIT_BF16, NS_F16_SCALED, NS_F32_ACC64).  They
+   change only how the product A Y of the residual R = I - (I - A) Y of
+   eq. (8) (Sec. 5.3) is computed; without one it is an FP64 MFMA product at
+   every level.  Any other combination is NS_ERR_UNSUPPORTED.
+     NS_RESID_LAST: the exact (FP64, or int8-emulated with NS_RESID_INT8)
+       residual only at the last two levels -- the residual the final update
+       uses and the reported final one; the earlier ones are products of the
+       working precision, whose error the next exact residual sees and the
+       update after it removes (Lemma 5.9: R_(n+1) = E(R_n) for the true
+       residual of each iterate).
+     NS_RESID_INT8(s): the residual product emulated from s int8 slices per
+       operand (1 <= s <= 8; s = 0 means 7): X = A by rows and Y by columns are
+       cut into signed 7-bit digits under a per-row / per-column power of two;
+       the s (s + 1) / 2 digit products with p + q <= s + 1 run on int8 MFMA
+       with exact int32 accumulation and are summed in FP64.  Error about
+       n 2^(e_i + f_j) (s + 1) 2^(-7 s), e_i and f_j the row and column
+       exponents.  The padded n is a multiple of 256; s n 127^2 must stay
+       below 2^31 (NS_ERR_RANGE otherwise). */
+#define NS_RESID_LAST 0x100
+#define NS_RESID_INT8(s) (0x200 | ((s) << 12))
+
 /* ---- status ----------------------------------------------------------- */
 enum ns_status {
   NS_OK = 0,
@@ -268,7 +291,9 @@ int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* to
 /* The same sums over the timed launches of one product engine only, named by
    the dtype that uses it: NS_F64 (FP64 products, including the FP64 residual
    products of the mixed forms), NS_F32 (FP32 products, including those of
-   NS_F32_ACC64), NS_SPLIT_BF16 or NS_F16_SCALED.  Resets nothing. */
+   NS_F32_ACC64), NS_SPLIT_BF16, NS_F16_SCALED, or NS_RESID_INT8(0) for the
+   int8-emulated residual products (one timed record per product, covering
+   all its diagonal launches).  Resets nothing. */
 int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* total_ms,
                             double* total_flops);
 

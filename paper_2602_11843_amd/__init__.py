@@ -25,6 +25,34 @@ METHODS = {"naive": NAIVE, "binary": BINARY, "radix9": RADIX9, "radix15": RADIX1
 F64, F32, SPLIT_BF16, F16_SCALED, F32_ACC64 = range(5)
 DTYPES = {"f64": F64, "f32": F32, "split_bf16": SPLIT_BF16, "f16_scaled": F16_SCALED,
           "f32_acc64": F32_ACC64}
+# residual-product modifiers, OR-ed into a dtype (see ns.h)
+RESID_LAST = 0x100
+
+
+def RESID_INT8(slices: int = 0) -> int:
+    return 0x200 | (int(slices) << 12)
+
+
+def dtype_code(dtype) -> int:
+    """The ns_dtype value of a dtype given as an int or as a name with
+    optional residual modifiers: "split_bf16+last", "split_bf16+i8" (7
+    slices), "f16_scaled+i8x5+last"."""
+    if not isinstance(dtype, str):
+        return int(dtype)
+    base, *mods = dtype.split("+")
+    if base not in DTYPES:
+        raise ValueError(f"unknown dtype {dtype!r}")
+    code = DTYPES[base]
+    for m in mods:
+        if m == "last":
+            code |= RESID_LAST
+        elif m == "i8":
+            code |= RESID_INT8(0)
+        elif m.startswith("i8x") and m[3:].isdigit():
+            code |= RESID_INT8(int(m[3:]))
+        else:
+            raise ValueError(f"unknown residual modifier {m!r} in {dtype!r}")
+    return code
 
 MAX_LEVELS = 64
 
@@ -136,7 +164,7 @@ def ns_plan(k: int, method):
 def ns_workspace_bytes(n: int, method, dtype) -> int:
     b = ctypes.c_size_t()
     _check(lib.ns_workspace_bytes(int(n), int(METHODS.get(method, method)),
-                                  int(DTYPES.get(dtype, dtype)), ctypes.byref(b)),
+                                  int(dtype_code(dtype)), ctypes.byref(b)),
            "ns_workspace_bytes")
     return b.value
 
@@ -206,7 +234,7 @@ class Handle:
         """The same sums over one product engine's launches (named by dtype)."""
         cnt, ms, fl = _I32(), _D(), _D()
         with self.lock:
-            _check(lib.ns_product_timing_dtype(self.ptr, int(DTYPES.get(dtype, dtype)),
+            _check(lib.ns_product_timing_dtype(self.ptr, int(dtype_code(dtype)),
                                                ctypes.byref(cnt), ctypes.byref(ms), ctypes.byref(fl)),
                    "ns_product_timing_dtype")
         return cnt.value, ms.value, fl.value
@@ -235,7 +263,7 @@ def _stream_ptr(stream):
 def io_dtype(dtype):
     """torch element type of A and out for a compute precision."""
     import torch
-    return torch.float32 if DTYPES.get(dtype, dtype) == F32 else torch.float64
+    return torch.float32 if (dtype_code(dtype) & 0xff) == F32 else torch.float64
 
 
 # Argument checks of the binding: the library receives bare pointers, so a
@@ -291,7 +319,7 @@ def ns_eval_ex(A, k: int, method="radix9", dtype="f64", out=None, handle: Option
     >= n via a 2-D stride).  Returns out (and the report dict if asked)."""
     import torch
     m = METHODS.get(method, method)
-    d = DTYPES.get(dtype, dtype)
+    d = dtype_code(dtype)
     _square("A", A, io_dtype(d))
     n = A.shape[0]
     if out is None:
@@ -317,7 +345,7 @@ def ns_eval_noalloc(A, k: int, method="radix9", dtype="f64", out=None, stream=No
     overlap on one GPU race on that array (see ns.h)."""
     import torch
     m = METHODS.get(method, method)
-    d = DTYPES.get(dtype, dtype)
+    d = dtype_code(dtype)
     _square("A", A, io_dtype(d))
     n = A.shape[0]
     if out is None:
@@ -335,7 +363,7 @@ def ns_eval_noalloc(A, k: int, method="radix9", dtype="f64", out=None, stream=No
 def ns_eval(A, k: int, method="radix9", dtype="f64", out=None):
     """The short form (per-device default handle, null stream, lda = n)."""
     import torch
-    m, d = METHODS.get(method, method), DTYPES.get(dtype, dtype)
+    m, d = METHODS.get(method, method), dtype_code(dtype)
     _square("A", A, io_dtype(d), contiguous=True)
     if out is None:
         out = torch.empty_like(A)
@@ -362,7 +390,7 @@ def ns_eval_batched(A_packed, offsets_dev, n_dev, n_host, k: int, method="radix9
         _check(lib.ns_eval_batched(h.ptr, _P(A_packed.data_ptr()), _P(offsets_dev.data_ptr()),
                                    _P(n_dev.data_ptr() if n_dev is not None else None),
                                    _P(n_host.data_ptr()), len(n_host), int(k),
-                                   int(METHODS.get(method, method)), int(DTYPES.get(dtype, dtype)),
+                                   int(METHODS.get(method, method)), int(dtype_code(dtype)),
                                    _P(out_packed.data_ptr()), _stream_ptr(stream),
                                    ctypes.byref(rep) if rep is not None else None),
                "ns_eval_batched")
@@ -387,7 +415,7 @@ def ns_eval_batched_loop(A_packed, offsets_host, n_host, k: int, method="radix9"
         _check(lib.ns_eval_batched_loop(h.ptr, _P(A_packed.data_ptr()), _P(offs.data_ptr()),
                                         _P(n_host.data_ptr()), len(n_host), int(k),
                                         int(METHODS.get(method, method)),
-                                        int(DTYPES.get(dtype, dtype)), _P(out_packed.data_ptr()),
+                                        int(dtype_code(dtype)), _P(out_packed.data_ptr()),
                                         _stream_ptr(stream)), "ns_eval_batched_loop")
     return out_packed
 

@@ -20,8 +20,8 @@ OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["gemm.hip", "panel.hip", "batched.hip", "util.hip", "noalloc.hip", "ns.cpp",
-           "radix15.cpp"]
+SOURCES = ["gemm.hip", "panel.hip", "ozaki.hip", "batched.hip", "util.hip", "noalloc.hip",
+           "ns.cpp", "radix15.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -27,6 +27,8 @@ enum Engine : int {
   ENG_F32 = 1,        // float operands, FP32 MFMA 16x16x4
   ENG_BF16X3 = 2,     // float operands split to bf16 hi/lo, 3 BF16 MFMA products
   ENG_F16S = 3,       // float operands scaled by 2^-e and rounded to fp16, 1 FP16 MFMA product
+  ENG_I8 = 4,         // double operands cut into int8 digit slices, int8 MFMA products with
+                      // exact int32 accumulation, summed in FP64 (ozaki.hip)
 };
 
 // Parameters of one n x n x n product C = X Y with a fused multi-output
@@ -85,6 +87,27 @@ hipError_t launch_to_panels(Engine e, const float* src, int n, int ld, int trans
                             const unsigned* amax, hipStream_t s);
 // host.X / host.Y point at the panels of X (rows) and Y (columns).
 hipError_t launch_gemm_panels(Engine e, const GemmParams& host, const GemmParams* dev, hipStream_t s);
+
+// FP64 products emulated from int8 slices (ozaki.hip).  The product kernel's
+// tile (the padded n must be a multiple of it); the slice count is at most
+// kMaxI8Slices.
+constexpr int kMaxI8Slices = 8;
+int i8_tile();
+// Row max-abs (rowmax, may be null) and column max-abs (colmax, may be null)
+// of an n x n FP64 matrix, as the bits of non-negative doubles, atomically into
+// arrays the caller has zeroed.  n a multiple of 256.
+hipError_t launch_maxabs_rc(const double* src, int n, unsigned long long* rowmax,
+                            unsigned long long* colmax, hipStream_t s);
+// The `slices` int8 digit planes (slices n^2 bytes) of src by rows
+// (transpose = 0, mx = row max-abs) or by columns (1, mx = column max-abs).
+hipError_t launch_i8_slices(const double* src, int n, int transpose, const unsigned long long* mx,
+                            int slices, void* dst, hipStream_t s);
+// X Y from the digit planes xs (of X, by rows) and ys (of Y, by columns): one
+// launch per diagonal of slice pairs, the partial sums in acc (n x n FP64),
+// the last launch applying the epilogue epi (device copy).
+hipError_t launch_gemm_i8(const void* xs, const void* ys, int n, int slices, double* acc,
+                          const unsigned long long* rowmax, const unsigned long long* colmax,
+                          const GemmParams* epi, hipStream_t s);
 
 // Elementwise helpers (util.hip).
 // dst (padded n_pad x n_pad, ld n_pad) <- src (n x n, lda) converted; the

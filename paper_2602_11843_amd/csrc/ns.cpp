@@ -123,15 +123,28 @@ struct Scalars {                          // layout of the scalar block in devic
 };
 static_assert(sizeof(Scalars) <= kScalarBytes, "scalar block too small");
 
+// A dtype argument is a base precision (low byte) plus residual-product
+// modifiers (NS_RESID_LAST, NS_RESID_INT8(s)).
+constexpr int kBaseMask = 0xff, kResidInt8 = 0x200, kSliceShift = 12;
+constexpr int kModifierBits = NS_RESID_LAST | kResidInt8 | (0xf << kSliceShift);
+int base_of(int dtype) { return dtype & kBaseMask; }
+bool resid_last(int dtype) { return (dtype & NS_RESID_LAST) != 0; }
+// slices of the int8-emulated residual product, 0 without the modifier
+int resid_slices(int dtype) {
+  if (!(dtype & kResidInt8)) return 0;
+  const int sl = (dtype >> kSliceShift) & 0xf;
+  return sl ? sl : 7;
+}
 bool is_mixed(int dtype) {
-  return dtype == NS_SPLIT_BF16 || dtype == NS_F16_SCALED || dtype == NS_F32_ACC64;
+  const int b = base_of(dtype);
+  return b == NS_SPLIT_BF16 || b == NS_F16_SCALED || b == NS_F32_ACC64;
 }
 bool is_residual(int method) {
   return method == NS_RADIX15 || method == NS_RADIX15C || method == NS_RADIX9_RESID ||
          method == NS_HENSEL;
 }
 Engine work_engine(int dtype) {
-  switch (dtype) {
+  switch (base_of(dtype)) {
     case NS_F64: return ENG_F64;
     case NS_F32: return ENG_F32;
     case NS_SPLIT_BF16: return ENG_BF16X3;
@@ -270,11 +283,12 @@ int plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gemms)
 
 int n_internal(int64_t n, int dtype) {
   const Engine e = work_engine(dtype);
-  int t = engine_tile(e, (int)n);
+  const int i8 = resid_slices(dtype) ? i8_tile() : 1;
+  int t = std::max(engine_tile(e, (int)n), i8);
   if (is_mixed(dtype)) t = std::max(t, engine_tile(ENG_F64, (int)n));
   int np = (int)((n + t - 1) / t * t);
   // the tile choice depends on the padded size; re-round if it changed
-  int t2 = engine_tile(e, np);
+  int t2 = std::max(engine_tile(e, np), i8);
   if (is_mixed(dtype)) t2 = std::max(t2, engine_tile(ENG_F64, np));
   return (int)((np + t2 - 1) / t2 * t2);
 }
@@ -297,16 +311,25 @@ void buffer_counts(int method, int dtype, int* nw, int* n64) {
   }
   *n64 = mixed ? (is_residual(method) ? 2 : 1) : 0;    // Y64 + A64, or S64
   // the 16-bit panels of a product's two operands (each at most an FP32 matrix)
-  if (dtype == NS_SPLIT_BF16 || dtype == NS_F16_SCALED) *nw += 2;
+  if (base_of(dtype) == NS_SPLIT_BF16 || base_of(dtype) == NS_F16_SCALED) *nw += 2;
+}
+
+// bytes of the int8-emulated residual's buffers: digit planes of both
+// operands, the FP64 partial sums, row and column max-abs
+size_t i8_bytes(int np, int slices) {
+  if (!slices) return 0;
+  const size_t mat = (size_t)np * np;
+  return 2 * slices * mat + 8 * mat + 2 * 8 * (size_t)np + 4 * 256;
 }
 
 size_t workspace_bytes(int64_t n, int method, int dtype) {
   const int np = n_internal(n, dtype);
   int nw, n64;
   buffer_counts(method, dtype, &nw, &n64);
-  const size_t w = (dtype == NS_F64) ? 8 : 4;
+  const size_t w = (base_of(dtype) == NS_F64) ? 8 : 4;
   const size_t mat = (size_t)np * np;
-  return kScalarBytes + mat * (nw * w + n64 * 8) + 256 * (nw + n64 + 1);
+  return kScalarBytes + mat * (nw * w + n64 * 8) + 256 * (nw + n64 + 1) +
+         i8_bytes(np, resid_slices(dtype));
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +350,7 @@ struct Out {
 
 // A recorded device operation of a call.
 struct Op {
-  enum Kind { GEMM, IDENTITY, AMAX, PANELS, ZERO, PAD, UNPAD } kind;
+  enum Kind { GEMM, IDENTITY, AMAX, PANELS, ZERO, PAD, UNPAD, MAXABS, SLICES } kind;
   Engine e;
   GemmParams p;      // GEMM
   bool panels;       // GEMM: X / Y are 16-bit panels
@@ -339,6 +362,14 @@ struct Op {
   int transpose;     // PANELS: 1 for a Y operand
   int src_f64;       // PAD / UNPAD: element type of the source
   int64_t n, ld;     // PAD / UNPAD: the caller's n and leading dimension; ZERO: bytes in n
+  // MAXABS: row max-abs into rmax, column max-abs into cmax (either may be
+  // null) of ptr.  SLICES: the digit planes of ptr (by columns if transpose)
+  // into dst, exponents from rmax.  GEMM on ENG_I8: X / Y are the digit
+  // planes, acc the partial sums, rmax / cmax the max-abs of X rows / Y columns.
+  unsigned long long* rmax;
+  unsigned long long* cmax;
+  double* acc;
+  int slices;
 };
 
 // Device memory of a call that allocates nothing (ns_eval_noalloc): the
@@ -364,6 +395,16 @@ struct Ctx {
   int next_amax = 0;
   int gemms = 0;
   int64_t launches = 0;     // product launches of the call (a pair counts once)
+  // int8-emulated residual products (NS_RESID_INT8): slice count, buffers, and
+  // the X operand whose planes are current (A, sliced once per call)
+  int slices = 0;
+  bool resid_last = false;
+  void* i8_x = nullptr;
+  void* i8_y = nullptr;
+  double* i8_acc = nullptr;
+  unsigned long long* i8_rmax = nullptr;
+  unsigned long long* i8_cmax = nullptr;
+  const void* i8_x_src = nullptr;
   int status = NS_OK;
   char* arena;
   size_t arena_off = 0;
@@ -462,7 +503,15 @@ struct Ctx {
     GemmParams& p = op.p;
     p.X = X.p;
     p.Y = Y.p;
-    if (panel_path(e, np)) {
+    if (e == ENG_I8) {
+      i8_operands(X, Y);
+      p.X = i8_x;
+      p.Y = i8_y;
+      op.acc = i8_acc;
+      op.rmax = i8_rmax;
+      op.cmax = i8_cmax;
+      op.slices = slices;
+    } else if (panel_path(e, np)) {
       panels(e, X, 0, panel_x);
       panels(e, Y, 1, panel_y);
       p.X = panel_x.p;
@@ -518,6 +567,40 @@ struct Ctx {
     }
   }
 
+  // Digit planes of the FP64 operands of an int8-emulated product: X (the
+  // copy of A, the same buffer at every level) once per call, Y every time.
+  void i8_operands(const Buf& X, const Buf& Y) {
+    if (i8_x_src != X.p) {
+      zero(i8_rmax, 8 * (size_t)np);
+      maxabs(X, i8_rmax, nullptr);
+      slice(X, 0, i8_rmax, i8_x);
+      i8_x_src = X.p;
+    }
+    zero(i8_cmax, 8 * (size_t)np);
+    maxabs(Y, nullptr, i8_cmax);
+    slice(Y, 1, i8_cmax, i8_y);
+  }
+
+  void maxabs(const Buf& b, unsigned long long* rmax, unsigned long long* cmax) {
+    Op op{};
+    op.kind = Op::MAXABS;
+    op.ptr = b.p;
+    op.rmax = rmax;
+    op.cmax = cmax;
+    ops.push_back(op);
+  }
+
+  void slice(const Buf& b, int transpose, unsigned long long* mx, void* dst) {
+    Op op{};
+    op.kind = Op::SLICES;
+    op.ptr = b.p;
+    op.transpose = transpose;
+    op.rmax = mx;
+    op.dst = dst;
+    op.slices = slices;
+    ops.push_back(op);
+  }
+
   // The last two recorded operations are independent products (neither reads
   // what the other writes): let them share one launch when both are plain
   // products of the same engine (not from panels) and one product's grid
@@ -528,7 +611,7 @@ struct Ctx {
     Op& a = ops[m - 2];
     const Op& b = ops[m - 1];
     if (a.kind == Op::GEMM && b.kind == Op::GEMM && !a.panels && !b.panels && a.e == b.e &&
-        gemm_grid(a.e, np) <= kPairMaxGrid)
+        a.e != ENG_I8 && gemm_grid(a.e, np) <= kPairMaxGrid)
       a.pair_next = true;
   }
 
@@ -638,6 +721,15 @@ struct Ctx {
                                 op.amax, s));
         continue;
       }
+      if (op.kind == Op::MAXABS) {
+        NS_HIP(launch_maxabs_rc(static_cast<const double*>(op.ptr), np, op.rmax, op.cmax, s));
+        continue;
+      }
+      if (op.kind == Op::SLICES) {
+        NS_HIP(launch_i8_slices(static_cast<const double*>(op.ptr), np, op.transpose, op.rmax,
+                                op.slices, op.dst, s));
+        continue;
+      }
       // an independent next product shares this launch
       const bool pair = op.pair_next && oi + 1 < ops.size() && ops[oi + 1].kind == Op::GEMM;
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -658,7 +750,9 @@ struct Ctx {
         NS_HIP(hipEventRecord(e0, s));
       }
       hipError_t err;
-      if (op.panels) err = launch_gemm_panels(op.e, op.p, pd + gi, s);
+      if (op.e == ENG_I8)
+        err = launch_gemm_i8(op.p.X, op.p.Y, np, op.slices, op.acc, op.rmax, op.cmax, pd + gi, s);
+      else if (op.panels) err = launch_gemm_panels(op.e, op.p, pd + gi, s);
       else if (pair) err = launch_gemm(op.e, op.p, pd + gi, s, &ops[oi + 1].p, pd + gi + 1);
       else err = launch_gemm(op.e, op.p, pd + gi, s);
       gi += pair ? 2 : 1;
@@ -914,9 +1008,14 @@ int run_schedule(Ctx& c, int method, int64_t k, int levels, const Buf& Ain_w, co
         else if (method == NS_RADIX9_RESID) { kernel_radix9(c, Rcur, U, X1, P, Q, T); Fm1 = &T; }
         else { kernel_radix15(c, k15, Rcur, P1, L2, R2, L3, R3, L4, R4, F); Fm1 = &F; }
         sum_update(c, Y, Y2, c.mixed ? &Y64 : nullptr, *Fm1);
-        // R = I - Y + A Y: the true residual of the new iterate
-        if (c.mixed) c.gemm(ENG_F64, A64, Y64, {Y64}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
-        else c.gemm(c.eng, A, Y, {Y}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
+        // R = I - Y + A Y: the true residual of the new iterate.  The mixed
+        // forms take A Y exactly (FP64 MFMA, or int8 slices) -- with
+        // NS_RESID_LAST only at the last two levels, the earlier ones in
+        // working precision against the FP64 Y
+        if (!c.mixed) c.gemm(c.eng, A, Y, {Y}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
+        else if (c.resid_last && lv < levels - 2)
+          c.gemm(c.eng, A, Y, {Y64}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
+        else c.gemm(c.slices ? ENG_I8 : ENG_F64, A64, Y64, {Y64}, {o(R, 1.0, -1.0, 0, 0, 1.0)}, lv);
         Rcur = R;
       }
       res->S = c.mixed ? Y64 : Y;
@@ -936,10 +1035,25 @@ int check_args(const void* A, int64_t n, int64_t lda, int64_t k, int method, int
   if (lda < n || ldo < n) return fail(NS_ERR_ARG, "leading dimension below n");
   if (k < 1) return fail(NS_ERR_ARG, "k must be >= 1 (got %lld)", (long long)k);
   if (method < NS_NAIVE || method > NS_RADIX15C) return fail(NS_ERR_ARG, "unknown method %d", method);
-  if (dtype < NS_F64 || dtype > NS_F32_ACC64) return fail(NS_ERR_ARG, "unknown dtype %d", dtype);
+  const int base = base_of(dtype);
+  if (base < NS_F64 || base > NS_F32_ACC64 || (dtype & ~(kBaseMask | kModifierBits)))
+    return fail(NS_ERR_ARG, "unknown dtype %d", dtype);
+  if (dtype & ~kBaseMask) {
+    if (!(dtype & kResidInt8) && (dtype >> kSliceShift))
+      return fail(NS_ERR_ARG, "slice count without NS_RESID_INT8 (dtype 0x%x)", dtype);
+    if (resid_slices(dtype) > kMaxI8Slices)
+      return fail(NS_ERR_ARG, "NS_RESID_INT8 takes 1 to %d slices", kMaxI8Slices);
+    if (!is_mixed(dtype) || !is_residual(method))
+      return fail(NS_ERR_UNSUPPORTED,
+                  "residual modifiers need a residual method in an FP64-accumulating dtype");
+    const int64_t np = n_internal(n, dtype);
+    if ((int64_t)resid_slices(dtype) * np * 127 * 127 >= ((int64_t)1 << 31))
+      return fail(NS_ERR_RANGE, "%d int8 slices at padded n = %lld overflow int32 accumulation",
+                  resid_slices(dtype), (long long)np);
+  }
   if (method == NS_NAIVE && is_mixed(dtype))
     return fail(NS_ERR_UNSUPPORTED, "the naive Horner form has no FP64-accumulated variant");
-  const size_t es = (dtype == NS_F32) ? 4 : 8;
+  const size_t es = (base == NS_F32) ? 4 : 8;
   const char* a0 = static_cast<const char*>(A);
   const char* a1 = a0 + ((size_t)(n - 1) * lda + n) * es;
   const char* b0 = static_cast<const char*>(out);
@@ -1004,11 +1118,24 @@ int eval_core(ns_handle* h, const FixedMem* fx, const void* A, int64_t n, int64_
   c.np = n_internal(n, dtype);
   c.eng = work_engine(dtype);
   c.mixed = is_mixed(dtype);
+  c.resid_last = resid_last(dtype);
+  c.slices = resid_slices(dtype);
   c.scal = reinterpret_cast<Scalars*>(ws);
   c.arena = ws + kScalarBytes;
   c.zero(c.scal, sizeof(Scalars));
+  if (c.slices) {
+    // the int8-emulated residual's buffers sit at the end of the workspace
+    const size_t mat = (size_t)c.np * c.np;
+    char* q = ws + need - i8_bytes(c.np, c.slices);
+    q = reinterpret_cast<char*>(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    c.i8_x = q;
+    c.i8_y = q + c.slices * mat;
+    c.i8_acc = reinterpret_cast<double*>(q + 2 * c.slices * mat);
+    c.i8_rmax = reinterpret_cast<unsigned long long*>(q + 2 * c.slices * mat + 8 * mat);
+    c.i8_cmax = c.i8_rmax + c.np;
+  }
 
-  const int in64 = (dtype != NS_F32);
+  const int in64 = (base_of(dtype) != NS_F32);
   const int W64 = (c.eng == ENG_F64);
   Buf Aw = c.take(W64);
   c.pad(A, in64, lda, Aw);
@@ -1129,7 +1256,8 @@ int ns_plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gem
 
 int ns_workspace_bytes(int64_t n, int method, int dtype, size_t* bytes) {
   if (!bytes) return fail(NS_ERR_ARG, "null output pointer");
-  if (n <= 0 || method < NS_NAIVE || method > NS_RADIX15C || dtype < NS_F64 || dtype > NS_F32_ACC64)
+  if (n <= 0 || method < NS_NAIVE || method > NS_RADIX15C || ns::base_of(dtype) > NS_F32_ACC64 ||
+      dtype < 0 || (dtype & ~(ns::kBaseMask | ns::kModifierBits)))
     return fail(NS_ERR_ARG, "bad arguments");
   *bytes = ns::workspace_bytes(n, method, dtype);
   return NS_OK;
@@ -1252,6 +1380,7 @@ int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* to
 int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* total_ms,
                             double* total_flops) {
   if (!h) return fail(NS_ERR_ARG, "null handle");
+  if (dtype == NS_RESID_INT8(0)) return sum_timing(h, ns::ENG_I8, count, total_ms, total_flops);
   if (dtype < NS_F64 || dtype > NS_F16_SCALED)
     return fail(NS_ERR_ARG, "dtype %d names no product engine", dtype);
   return sum_timing(h, ns::work_engine_of(dtype), count, total_ms, total_flops);

@@ -1,0 +1,337 @@
+// FP64 products emulated from int8 slices with exact integer accumulation
+// (Ozaki's error-free splitting), for the residual product A Y of
+// R = I - (I - A) Y (Sec. 5.3, eq. (8)) in the FP64-accumulating precision
+// forms.
+//
+// Splitting.  Each row i of X gets the exponent e_i with max_j |X_ij| < 2^e_i;
+// x = X_ij 2^-e_i lies in (-1, 1) and is cut into s signed 7-bit digits by
+//   t = 128 x,  d = trunc(t) in [-127, 127],  x <- t - d       (all exact),
+// so X_ij = 2^e_i (sum_p d_p 2^-7p + r 2^-7s), |r| < 1.  Y is cut the same way
+// by columns (exponents f_j).  Then
+//   (X Y)_ij ~ 2^(e_i + f_j) sum_{p + q <= s + 1} 2^-7(p+q) (D_p E_q)_ij,
+// every D_p E_q an int8 product with int32 accumulation, exact while
+// K 127^2 (s - 1) < 2^31 (K = n up to 16384 for s = 8).  The pairs of one
+// diagonal d = p + q share their scale, so one diagonal is ONE int8 product
+// over the k-concatenation of its d - 1 slice pairs.  The dropped pairs and
+// the digit remainders bound the error by about n 2^(e_i + f_j) (s + 1) 2^-7s.
+//
+// Layout.  The digits of plane p (p = 0..s-1) form a panel of the n x n int8
+// matrix M (X by rows; Y^T, i.e. Y by columns) with the byte layout of the
+// 16-bit panels of an n x n/2 matrix: 16 x 64-byte blocks of 1 KB, block (rb,
+// kb) at byte (kb (n/16) + rb) 1024, row rr's 16-byte chunk c at rr 64 +
+// 16 (c ^ swz(rr)).  So the product kernel's loader and fragment reads are
+// the 16-bit panel kernel's, in 16-bit units.
+//
+// Product.  One launch per diagonal, d = s + 1 down to 2, each over K = (d - 1) n:
+// k-chunk c reads X plane j = c / (n/64) and Y plane d - 2 - j.  The launch of
+// the last diagonal adds the FP64 partial sum of the earlier ones, scales by
+// 2^(e_i + f_j) and applies the product's affine epilogue; the others write
+// their partial sum (FP64) to an accumulator matrix.
+#include "gemm_device.h"
+
+namespace ns {
+namespace dev {
+namespace {
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned long long u64;
+
+__device__ __forceinline__ int swz8(int rr) { return ((rr >> 1) ^ (rr >> 3)) & 3; }
+
+// smallest e with max < 2^e for the bits of a non-negative double max (0 for 0)
+__device__ __forceinline__ int exp_above(u64 bits) {
+  if (bits == 0) return 0;
+  const int ef = (int)((bits >> 52) & 0x7ff);
+  return ef == 0 ? -1022 : ef - 1022;
+}
+__device__ __forceinline__ bool max_finite(u64 bits) { return ((bits >> 52) & 0x7ff) != 0x7ff; }
+
+// Row and/or column max-abs of an n x n FP64 matrix, as the bits of
+// non-negative doubles, atomically into zeroed arrays.  Block: 64 rows x 256
+// columns, one column per thread.  NaN entries are recorded as Inf.
+__global__ __launch_bounds__(256) void maxabs_rc_kernel(const double* __restrict__ src, int n,
+                                                        u64* __restrict__ rowmax,
+                                                        u64* __restrict__ colmax) {
+  __shared__ double wred[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = blockIdx.x * 256 + tid, r0 = blockIdx.y * 64;
+  double cm = 0.0;
+  for (int r = 0; r < 64; ++r) {
+    double v = fabs(src[(size_t)(r0 + r) * n + c]);
+    if (v != v) v = INFINITY;
+    cm = fmax(cm, v);
+    if (rowmax) {
+      double m = v;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+      if (lane == 0) wred[wave][r] = m;
+    }
+  }
+  if (colmax) atomicMax(&colmax[c], (u64)__double_as_longlong(cm));
+  if (rowmax) {
+    __syncthreads();
+    if (tid < 64) {
+      const double m = fmax(fmax(wred[0][tid], wred[1][tid]), fmax(wred[2][tid], wred[3][tid]));
+      atomicMax(&rowmax[r0 + tid], (u64)__double_as_longlong(m));
+    }
+  }
+}
+
+// The s digit planes of an n x n FP64 matrix (transpose = 0: M = src by rows;
+// 1: M = src^T, i.e. by columns), with the exponent of M's row r from mx[r].
+// One workgroup per 64 x 64 region of M, staged in LDS as M[r][k]; each thread
+// then writes one 16-byte chunk of every plane.
+__global__ __launch_bounds__(256) void slices_kernel(const double* __restrict__ src, int n,
+                                                     int transpose, const u64* __restrict__ mx,
+                                                     int s, int8_t* __restrict__ dst) {
+  __shared__ double t[64][65];
+  const int r0 = 64 * blockIdx.y, k0 = 64 * blockIdx.x, tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int v = tid + 256 * i, a = v >> 5, c2 = (v & 31) * 2;
+    if (!transpose) {
+      const double2 x = *reinterpret_cast<const double2*>(src + (size_t)(r0 + a) * n + k0 + c2);
+      t[a][c2] = x.x;
+      t[a][c2 + 1] = x.y;
+    } else {   // src row k0 + a holds M[r0 + c2 ..][k0 + a]
+      const double2 x = *reinterpret_cast<const double2*>(src + (size_t)(k0 + a) * n + r0 + c2);
+      t[c2][a] = x.x;
+      t[c2 + 1][a] = x.y;
+    }
+  }
+  __syncthreads();
+  const int blk = tid >> 6, pos = tid & 63, rr = pos >> 2, pc = pos & 3;
+  const int r = 16 * blk + rr, kk = 16 * (pc ^ swz8(rr));
+  const int e = exp_above(mx[r0 + r]);
+  double x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const double v = ldexp(t[r][kk + i], -e);
+    x[i] = (v == v && fabs(v) < 1.0) ? v : 0.0;   // non-finite rows are flagged by the product
+  }
+  const size_t plane = (size_t)n * n;
+  const size_t off = ((size_t)(k0 / 64) * (n / 16) + (r0 / 16 + blk)) * 1024 + 16 * pos;
+  for (int p = 0; p < s; ++p) {
+    i32x4 w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      unsigned b = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double tt = 128.0 * x[4 * q + i];
+        const double d = trunc(tt);
+        x[4 * q + i] = tt - d;
+        b |= ((unsigned)(int)d & 0xffu) << (8 * i);
+      }
+      w[q] = (int)b;
+    }
+    *reinterpret_cast<i32x4*>(dst + p * plane + off) = w;
+  }
+}
+
+// One diagonal of the emulated product.
+struct I8Args {
+  const uint16_t* X;        // digit planes of X (rows), viewed as 16-bit panels
+  const uint16_t* Y;        // digit planes of Y (columns)
+  int n;                    // padded n, a multiple of 256
+  int d;                    // diagonal p + q (2 .. s + 1)
+  int first, last;          // first: no partial sum to add; last: apply the epilogue
+  double* acc;              // FP64 partial sums, n x n
+  const u64* rowmax;        // X row max-abs bits
+  const u64* colmax;        // Y column max-abs bits
+  const GemmParams* epi;    // the product's epilogue (device), read by the last launch
+};
+
+// 256 x 256 tile, 8 waves of 128 x 64 (4 x 2 fragments of
+// v_mfma_i32_32x32x32_i8), k-chunk 64 int8 (two MFMA steps), two LDS stages.
+struct PolI8 {
+  static constexpr int NWM = 2, NWN = 4, NI = 4, NJ = 2;
+  static constexpr int WTM = 32 * NI, WTN = 32 * NJ;
+  static constexpr int BM = NWM * WTM, BN = NWN * WTN;
+  static constexpr int BK16 = 32;                    // k-chunk in 16-bit units (64 int8)
+  static constexpr int THREADS = 64 * NWM * NWN, NW = THREADS / 64;
+  static constexpr int A_BLK = BM / 16, B_BLK = BN / 16;   // 1 KB blocks per chunk
+  static constexpr int A_EL = A_BLK * 512, STAGE_EL = (A_BLK + B_BLK) * 512;
+  static constexpr int STAGES = 2;
+  static constexpr int PER_WAVE = (A_BLK + B_BLK) / NW;
+  static_assert((A_BLK + B_BLK) % NW == 0, "loader blocks per wave");
+  static constexpr int EFR = 2;                      // fragment-rows per epilogue pass
+  static constexpr int CPITCH = BN + 4;              // epilogue staging, int32
+  static constexpr int EPI_EL = 32 * EFR * CPITCH * 2;
+  static constexpr int SMEM_EL = STAGES * STAGE_EL > EPI_EL ? STAGES * STAGE_EL : EPI_EL;
+};
+
+template <class Q>
+__global__ __launch_bounds__(Q::THREADS, 1) void gemm_i8_kernel(const I8Args args) {
+  __shared__ __align__(16) uint16_t smem[Q::SMEM_EL];
+  const int n = args.n;
+  const int tiles_m = n / Q::BM, tiles_n = n / Q::BN;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int row0 = tm * Q::BM, col0 = tn * Q::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / Q::NWN, wn = wave % Q::NWN;
+  const size_t plane16 = (size_t)n * n / 2;          // one digit plane, 16-bit units
+  const size_t chunk_el = (size_t)n * Q::BK16;       // one k-chunk of all row blocks
+  const int nkp = n / 64;                            // k-chunks per plane
+  const int nk = (args.d - 1) * nkp;
+
+  uint32_t goff[Q::PER_WAVE];
+  bool isx[Q::PER_WAVE];
+  int loff[Q::PER_WAVE];
+#pragma unroll
+  for (int i = 0; i < Q::PER_WAVE; ++i) {
+    const int b = wave + i * Q::NW;
+    isx[i] = b < Q::A_BLK;
+    goff[i] = isx[i] ? (uint32_t)((row0 / 16 + b) * 512 + 8 * lane)
+                     : (uint32_t)((col0 / 16 + (b - Q::A_BLK)) * 512 + 8 * lane);
+    loff[i] = b * 512;
+  }
+  auto issue = [&](int c, int stage) {
+    const int j = c / nkp, kc = c - j * nkp;
+    const uint16_t* xs = args.X + (size_t)j * plane16 + (size_t)kc * chunk_el;
+    const uint16_t* ys = args.Y + (size_t)(args.d - 2 - j) * plane16 + (size_t)kc * chunk_el;
+#pragma unroll
+    for (int i = 0; i < Q::PER_WAVE; ++i)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)((isx[i] ? xs : ys) + goff[i]),
+          (__attribute__((address_space(3))) void*)(smem + stage * Q::STAGE_EL + loff[i]), 16, 0, 0);
+  };
+
+  const int fr = lane & 31, rr = fr & 15;
+  const int lrow = (fr >> 4) * 512 + rr * 32;
+  const int cofs0 = 8 * ((lane >> 5) ^ swz8(rr));
+  const int cofs1 = 8 * ((2 + (lane >> 5)) ^ swz8(rr));
+
+  i32x16 acc[Q::NI][Q::NJ];
+#pragma unroll
+  for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+    for (int j = 0; j < Q::NJ; ++j) acc[i][j] = i32x16{};
+
+  issue(0, 0);
+  wait_vmcnt<0>();
+  __syncthreads();
+  int cur = 0;
+  for (int kc = 0; kc < nk; ++kc) {
+    if (kc + 1 < nk) issue(kc + 1, cur ^ 1);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const uint16_t* As = smem + cur * Q::STAGE_EL;
+      const uint16_t* Bs = As + Q::A_EL;
+      const int co = ks ? cofs1 : cofs0;
+      i32x4 a[Q::NI], b[Q::NJ];
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i)
+        a[i] = *reinterpret_cast<const i32x4*>(As + (wm * Q::WTM / 16 + 2 * i) * 512 + lrow + co);
+#pragma unroll
+      for (int j = 0; j < Q::NJ; ++j)
+        b[j] = *reinterpret_cast<const i32x4*>(Bs + (wn * Q::WTN / 16 + 2 * j) * 512 + lrow + co);
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i)
+#pragma unroll
+        for (int j = 0; j < Q::NJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // chunk kc + 1 in LDS and every wave done with chunk kc before the next
+    // iteration overwrites this stage
+    wait_vmcnt<0>();
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // epilogue: stage EFR fragment-rows of int32 results at a time; each thread
+  // then handles row-contiguous vectors of 4
+  int* C = reinterpret_cast<int*>(smem);
+  constexpr int VEC = 4, VPR = Q::BN / VEC;
+  constexpr int PPW = Q::NI / Q::EFR, PROWS = 32 * Q::EFR;
+  const double dscale = ldexp(1.0, -7 * args.d);
+  EpiState st{0.0, 0.f, 0};
+  const GemmParams* p = args.last ? args.epi : nullptr;
+#pragma unroll 1
+  for (int pass = 0; pass < Q::NWM * PPW; ++pass) {
+    const int pw = pass / PPW, pi = pass % PPW;
+    if (wm == pw) {
+#pragma unroll
+      for (int i = 0; i < Q::NI; ++i) {
+        if (i / Q::EFR != pi) continue;
+#pragma unroll
+        for (int j = 0; j < Q::NJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            C[(32 * (i % Q::EFR) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * Q::CPITCH + wn * Q::WTN +
+              32 * j + (lane & 31)] = acc[i][j][r];
+      }
+    }
+    __syncthreads();
+    const int grow = row0 + pw * Q::WTM + pi * PROWS;
+    for (int v = tid; v < PROWS * VPR; v += Q::THREADS) {
+      const int r = v / VPR, cv = (v % VPR) * VEC;
+      const int row = grow + r, col = col0 + cv;
+      const size_t idx = (size_t)row * n + col;
+      double c[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e] * dscale;
+      if (!args.first) {
+        const double2 a0 = *reinterpret_cast<const double2*>(args.acc + idx);
+        const double2 a1 = *reinterpret_cast<const double2*>(args.acc + idx + 2);
+        c[0] += a0.x; c[1] += a0.y; c[2] += a1.x; c[3] += a1.y;
+      }
+      if (!args.last) {
+        *reinterpret_cast<double2*>(args.acc + idx) = make_double2(c[0], c[1]);
+        *reinterpret_cast<double2*>(args.acc + idx + 2) = make_double2(c[2], c[3]);
+        continue;
+      }
+      const u64 rb = args.rowmax[row];
+      const int er = exp_above(rb);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const u64 cb = args.colmax[col + e];
+        c[e] = (max_finite(rb) && max_finite(cb)) ? ldexp(c[e], er + exp_above(cb)) : NAN;
+      }
+      epi_vec<VEC>(*p, row, col, c, st);
+    }
+    __syncthreads();
+  }
+  if (args.last) publish_stats<Q::THREADS>(*p, st, reinterpret_cast<double*>(smem));
+}
+
+}  // namespace
+}  // namespace dev
+
+int i8_tile() { return dev::PolI8::BM; }
+
+hipError_t launch_maxabs_rc(const double* src, int n, unsigned long long* rowmax,
+                            unsigned long long* colmax, hipStream_t s) {
+  if (n % 256 || (!rowmax && !colmax)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dev::maxabs_rc_kernel, dim3(n / 256, n / 64), dim3(256), 0, s, src, n, rowmax,
+                     colmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_i8_slices(const double* src, int n, int transpose, const unsigned long long* mx,
+                            int slices, void* dst, hipStream_t s) {
+  if (n % 64 || slices < 1 || slices > kMaxI8Slices) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dev::slices_kernel, dim3(n / 64, n / 64), dim3(256), 0, s, src, n, transpose,
+                     mx, slices, static_cast<int8_t*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_i8(const void* xs, const void* ys, int n, int slices, double* acc,
+                          const unsigned long long* rowmax, const unsigned long long* colmax,
+                          const GemmParams* epi, hipStream_t s) {
+  using Q = dev::PolI8;
+  if (n % Q::BM || n % Q::BN || slices < 1 || slices > kMaxI8Slices) return hipErrorInvalidValue;
+  const int grid = (n / Q::BM) * (n / Q::BN);
+  for (int d = slices + 1; d >= 2; --d) {
+    const dev::I8Args a{static_cast<const uint16_t*>(xs), static_cast<const uint16_t*>(ys), n, d,
+                        d == slices + 1, d == 2, acc, rowmax, colmax, epi};
+    hipLaunchKernelGGL(dev::gemm_i8_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ns

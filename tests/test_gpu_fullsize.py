@@ -54,6 +54,10 @@ def precision_input():
     ("radix9", "f16_scaled", 1e-2),
     ("radix9_resid", "split_bf16", 1e-8),
     ("radix9_resid", "f16_scaled", 1e-6),
+    # the residual-product variants (measured 7.8e-11, 7.6e-11, 3.8e-10)
+    ("radix9_resid", "split_bf16+last", 1e-8),
+    ("radix9_resid", "split_bf16+i8", 1e-8),
+    ("radix9_resid", "split_bf16+i8x6", 1e-8),
 ])
 def test_precision_workload(ns, precision_input, method, dtype, tol):
     w, ref = precision_input
