@@ -214,10 +214,11 @@ def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate
 
 
 def rnd(d):
+    """Floats to 7 significant digits (errors of 1e-15 stay visible)."""
     out = {}
     for k, v in d.items():
         if isinstance(v, float):
-            out[k] = round(v, 6)
+            out[k] = float(f"{v:.7g}")
         elif isinstance(v, dict):
             out[k] = rnd(v)
         else:
@@ -547,6 +548,46 @@ MAIN_LEG = {"precision_sym": "radix9:f64", "gaussian_rho": "radix15c:f32:rho0.99
             "small_symmetric": "radix9:f64"}
 
 
+def vendor_reference(torch, n=8192, reps=10):
+    """The vendor BLAS on the same part, as a practical ceiling beside each
+    engine's roofline: torch.matmul of two n x n matrices per precision (and
+    torch._int_mm for int8), event-timed on the current stream.  Run only;
+    nothing of it is used by the library."""
+    out = {}
+    cases = [("f64", torch.float64, PEAK["f64"]), ("f32", torch.float32, PEAK["f32"]),
+             ("bf16", torch.bfloat16, PEAK["split_bf16"]), ("f16", torch.float16, PEAK["f16_scaled"]),
+             ("i8", torch.int8, PEAK["i8"])]
+    for name, dt, peak in cases:
+        try:
+            if dt == torch.int8:
+                a = torch.randint(-127, 128, (n, n), dtype=dt, device="cuda")
+                b = torch.randint(-127, 128, (n, n), dtype=dt, device="cuda")
+                fn = lambda: torch._int_mm(a, b)          # noqa: E731
+            else:
+                a = torch.randn((n, n), device="cuda").to(dt)
+                b = torch.randn((n, n), device="cuda").to(dt)
+                fn = lambda: torch.matmul(a, b)           # noqa: E731
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rate = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+            out[name] = {"ms": round(ms, 4), "rate": round(rate, 2), "unit": "TOP/s" if name == "i8" else "TFLOP/s",
+                         "frac_of_peak": round(rate / peak, 4)}
+            log(f"[bench] vendor {name} n={n}: {ms:.3f} ms, {rate:.1f} ({rate / peak:.3f} of peak)")
+            del a, b
+        except Exception as e:                            # noqa: BLE001  (a missing vendor path)
+            out[name] = {"error": str(e)[:120]}
+    torch.cuda.empty_cache()
+    return out
+
+
 def speedups(res, pairs):
     """wall-time ratio of the squaring leg over each radix leg, beside the
     product-count prediction."""
@@ -608,7 +649,8 @@ def main():
     line, main_key = build_line(args, "precision_sym", res, cpu, info)
     if line["roofline"] is not None and main_key == "radix9:f64":
         line["roofline"]["traffic"] = measured_traffic("pmc_gemm_f64_big_precision_sym.md")
-        line["roofline"]["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        line["roofline"]["traffic_unit"] = ("bytes per launch between L2 and the memory side (MALL or HBM): "
+                                           "FETCH_SIZE + WRITE_SIZE, copy-calibrated")
     line["cpu_baseline"] = cpu
     legs = {f"precision_sym/{k}": rnd(v) for k, v in res.items()}
     line["speedup_over_binary"] = speedups(res, [("radix9:f64", "binary:f64")])
@@ -625,6 +667,7 @@ def main():
         if name == "small_symmetric":
             line["speedup_over_binary_small_symmetric"] = speedups(r, [("radix9:f64", "binary:f64")])
     line["legs"] = legs
+    line["vendor_gemm_reference_n8192"] = vendor_reference(torch)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -87,3 +87,10 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode != 0
     assert "one GPU" in (p.stdout + p.stderr)
+
+
+def test_rounding_keeps_small_errors_visible():
+    import bench
+    r = bench.rnd({"err": 4.643212e-15, "ms": 244.13781234, "nested": {"e": 7.5881e-11}})
+    assert r["err"] == 4.643212e-15 and r["nested"]["e"] == 7.5881e-11
+    assert r["ms"] == 244.1378
