@@ -195,6 +195,7 @@ def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate
             fn()
         torch.cuda.synchronize()
     per_engine = {e: h.ns_product_timing_dtype(ns.RESID_INT8(0) if e == "i8" else e) for e in ENGINES}
+    launches = h.ns_product_timing_launches()
     cnt, kms, kfl = h.ns_product_timing(reset=True)
     h.ns_set_product_timing(False)
     _, rep = ns.ns_eval_ex(A, k, method, dtype, out=out, handle=h, stream=stream, report=True)
@@ -202,7 +203,15 @@ def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate
     rooflines = {e: engine_roofline(e, st, rep["n_internal"], resid_slices(dtype))
                  for e, st in per_engine.items() if st[0]}
     dominant = max(rooflines, key=lambda e: per_engine[e][1]) if rooflines else None
+    # per-level split of the last timed call (its launches are the last ones recorded)
+    per_call = rep["product_launches"]
+    last = [ms for ms, _ in launches[-per_call:]] if per_call and len(launches) >= per_call else []
+    level_ms = None
+    if last and levels and per_call % levels == 0:
+        per_lv = per_call // levels
+        level_ms = [round(sum(last[i * per_lv:(i + 1) * per_lv]), 4) for i in range(levels)]
     r = {"ms": sec * 1e3, "tflops": flops / sec / 1e12, "products": products, "k_eff": k_eff,
+         "level_ms_last_call": level_ms,
          "levels": levels, "product_launches_per_call": rep["product_launches"],
          "launches_timed": cnt, "kernel_ms_per_call": kms / steps,
          "roofline": rooflines.get(dominant), "rooflines_by_engine": rooflines,

@@ -297,6 +297,14 @@ int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* to
 int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* total_ms,
                             double* total_flops);
 
+/* The timed launches one by one, in launch order, since the last reset: up to
+   cap entries of kernel milliseconds (ms) and product engine (engine: the
+   dtype naming it, as for ns_product_timing_dtype; either array may be
+   null).  *count receives the number of timed launches (which may exceed
+   cap).  Per-level time splits of a call are sums over its launches. */
+int ns_product_timing_launches(ns_handle* h, int32_t cap, float* ms, int32_t* engine,
+                               int32_t* count);
+
 const char* ns_status_string(int status);
 const char* ns_last_error(void);
 

@@ -123,6 +123,8 @@ _SIGNATURES = {
                                          ctypes.POINTER(_D), ctypes.c_int]),
     "ns_product_timing_dtype": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I32),
                                                ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "ns_product_timing_launches": (ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_float),
+                                                  ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "ns_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ns_last_error": (ctypes.c_char_p, []),
 }
@@ -229,6 +231,19 @@ class Handle:
             _check(lib.ns_product_timing(self.ptr, ctypes.byref(cnt), ctypes.byref(ms),
                                          ctypes.byref(fl), int(bool(reset))), "ns_product_timing")
         return cnt.value, ms.value, fl.value
+
+    def ns_product_timing_launches(self):
+        """[(ms, engine dtype value)] of every timed launch since the last reset, in order."""
+        cnt = _I32()
+        with self.lock:
+            _check(lib.ns_product_timing_launches(self.ptr, 0, None, None, ctypes.byref(cnt)),
+                   "ns_product_timing_launches")
+            n = cnt.value
+            ms = (ctypes.c_float * max(n, 1))()
+            eng = (_I32 * max(n, 1))()
+            _check(lib.ns_product_timing_launches(self.ptr, n, ms, eng, ctypes.byref(cnt)),
+                   "ns_product_timing_launches")
+        return [(ms[i], eng[i]) for i in range(n)]
 
     def ns_product_timing_dtype(self, dtype):
         """The same sums over one product engine's launches (named by dtype)."""

@@ -1386,6 +1386,25 @@ int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* tot
   return sum_timing(h, ns::work_engine_of(dtype), count, total_ms, total_flops);
 }
 
+int ns_product_timing_launches(ns_handle* h, int32_t cap, float* ms, int32_t* engine,
+                               int32_t* count) {
+  if (!h || cap < 0) return fail(NS_ERR_ARG, "bad arguments");
+  int32_t i = 0;
+  for (size_t k = 0; k < h->ev_used; ++k, ++i) {
+    if (i >= cap) continue;
+    const auto& t = h->ev[k];
+    if (ms) {
+      NS_HIP(hipEventSynchronize(t.e1));
+      NS_HIP(hipEventElapsedTime(&ms[i], t.e0, t.e1));
+    }
+    // engines are named by the dtype that uses them; the int8 residual engine
+    // by its modifier
+    if (engine) engine[i] = t.engine == ns::ENG_I8 ? NS_RESID_INT8(0) : t.engine;
+  }
+  if (count) *count = (int32_t)h->ev_used;
+  return NS_OK;
+}
+
 const char* ns_status_string(int status) {
   switch (status) {
     case NS_OK: return "ok";

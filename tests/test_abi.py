@@ -48,7 +48,8 @@ def test_binding_names_match_abi(ns):
     for name in _declared_functions():
         if name in ("ns_create", "ns_destroy", "ns_last_error"):
             continue
-        if name in ("ns_set_product_timing", "ns_product_timing", "ns_product_timing_dtype"):
+        if name in ("ns_set_product_timing", "ns_product_timing", "ns_product_timing_dtype",
+                    "ns_product_timing_launches"):
             assert hasattr(ns.Handle, name)
         else:
             assert hasattr(ns, name), name

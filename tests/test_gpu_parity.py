@@ -355,3 +355,29 @@ def test_mixed_matches_closed_form_at_k_not_a_power(ns):
         closed = series.spectral_form(w.Q, w.lam, k)
         assert rep["k_eff"] == k
         assert_close(got, closed, 1e-12, f"mixed k={k} vs closed form")
+
+
+def test_product_timing_records_every_launch(ns):
+    """Per-launch timing: one record per product launch of each call, in
+    order, engines named by dtype; their sum equals the aggregate, and the
+    launches of a call group into its levels (radix-9 at n = 2048, FP64: five
+    products per level in four launches, the independent sum and power
+    updates sharing one grid)."""
+    w = workloads.symmetric(2048, 0.9, 5)
+    A = torch.from_numpy(w.A).cuda()
+    h = ns.Handle(torch.cuda.current_device())
+    try:
+        h.ns_set_product_timing(True)
+        h.ns_product_timing(reset=True)
+        for _ in range(2):
+            _, rep = ns.ns_eval_ex(A, 729, "radix9", "f64", handle=h, report=True)
+        launches = h.ns_product_timing_launches()
+        cnt, total, _ = h.ns_product_timing(reset=True)
+        h.ns_set_product_timing(False)
+    finally:
+        h.close()
+    assert rep["product_launches"] == 12 and rep["gemms_performed"] == 15
+    assert len(launches) == cnt == 2 * rep["product_launches"]
+    assert all(e == ns.F64 and ms > 0 for ms, e in launches)
+    assert abs(sum(ms for ms, _ in launches) - total) < 1e-3 * total
+    say(f"   per level (last call): {[round(sum(ms for ms, _ in launches[12 + 4 * i:16 + 4 * i]), 3) for i in range(3)]} ms")
