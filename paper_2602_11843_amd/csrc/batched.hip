@@ -132,11 +132,25 @@ __device__ __forceinline__ void one_matrix(const BatchArgs& a, int m, int n, flo
   for (int i = 0; i < kSlotMats; ++i) buf[i] = slot + i * mat;
   float *B = buf[0], *B2 = buf[1], *S = buf[2], *S2 = buf[3], *U = buf[4], *X1 = buf[5],
         *Pm = buf[6], *Q = buf[7], *T = buf[8];
+  // B <- A zero-padded to np, S <- I: four consecutive elements of a padded
+  // row per thread step; np is 64, 128 or 256, so row and column are shifts
+  // (a 64-bit division per element took 60 us of an n = 256 matrix's 1 ms)
+  const int lg = np == 64 ? 6 : np == 128 ? 7 : 8;
   const float* Am = a.A + a.off[m];
-  for (size_t i = threadIdx.x; i < mat; i += kThreads) {
-    const int r = (int)(i / np), c = (int)(i % np);
-    B[i] = (r < n && c < n) ? Am[(size_t)r * n + c] : 0.f;
-    S[i] = (r == c) ? 1.f : 0.f;
+  for (int i = threadIdx.x; i < (np * np) >> 2; i += kThreads) {
+    const int r = i >> (lg - 2), c = (i & ((np >> 2) - 1)) << 2;
+    float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r < n) {
+      const float* src = Am + (size_t)r * n + c;
+      if (c < n) b.x = src[0];
+      if (c + 1 < n) b.y = src[1];
+      if (c + 2 < n) b.z = src[2];
+      if (c + 3 < n) b.w = src[3];
+    }
+    *reinterpret_cast<float4*>(B + ((size_t)r << lg) + c) = b;
+    *reinterpret_cast<float4*>(S + ((size_t)r << lg) + c) =
+        make_float4(r == c ? 1.f : 0.f, r == c + 1 ? 1.f : 0.f, r == c + 2 ? 1.f : 0.f,
+                    r == c + 3 ? 1.f : 0.f);
   }
   __syncthreads();
   for (int lv = 0; lv < a.levels; ++lv) {
@@ -205,10 +219,17 @@ __device__ __forceinline__ void one_matrix(const BatchArgs& a, int m, int n, flo
     float* t = S; S = S2; S2 = t;
     t = B; B = B2; B2 = t;
   }
+  // out <- the top-left n x n block of S, four elements of a row per step
+  const int q = (n + 3) >> 2;
   float* Om = a.out + a.off[m];
-  for (size_t i = threadIdx.x; i < (size_t)n * n; i += kThreads) {
-    const int r = (int)(i / n), c = (int)(i % n);
-    Om[i] = S[(size_t)r * np + c];
+  for (int i = threadIdx.x; i < n * q; i += kThreads) {
+    const int r = i / q, c = (i - r * q) << 2;
+    const float4 v = *reinterpret_cast<const float4*>(S + ((size_t)r << lg) + c);
+    float* dst = Om + (size_t)r * n + c;
+    dst[0] = v.x;
+    if (c + 1 < n) dst[1] = v.y;
+    if (c + 2 < n) dst[2] = v.z;
+    if (c + 3 < n) dst[3] = v.w;
   }
   __syncthreads();
 }
@@ -216,7 +237,11 @@ __device__ __forceinline__ void one_matrix(const BatchArgs& a, int m, int n, flo
 using Small = PolF32<2, 2, 2, 2>;     // 64 x 64 tiles for n <= 64
 // 128 x 256 tiles with the direct-to-LDS k-loop for n in (128, 256]: the slot
 // is padded to 256 there, so a tile row is one whole 1 KB slot row
-using Wide = PolF32<2, 2, 4, 8>;
+struct Wide : PolF32<2, 2, 4, 8> {
+  // three LDS stages: two k-chunks in flight behind the one the matrix cores
+  // work on (74 KB of LDS, still two workgroups per CU)
+  static constexpr int DMA_STAGES = 3;
+};
 static_assert(Wide::BN == kMaxBatchN && DmaShape<Wide>::OK, "wide tile spans a padded slot row");
 
 template <class A, class B>
