@@ -21,7 +21,8 @@ from oracle import series
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "f32_acc64": 1e-5, "split_bf16": 1e-4, "f16_scaled": 1e-2}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32_acc64": 1e-5, "split_bf16": 1e-4, "f16_scaled": 1e-2,
+       "split_bf16+i8": 1e-4}
 
 # (method, dtype, first n, second n, k): both tile families of the small sizes,
 # ragged tails, the mixed forms with their FP64 copies and max-abs slots
@@ -32,6 +33,7 @@ CASES = [
     ("radix9", "f16_scaled", 300, 37, 81),
     ("radix15c", "f64", 300, 129, 3375),
     ("mixed", "f32_acc64", 129, 65, 100),
+    ("radix9_resid", "split_bf16+i8", 300, 64, 729),
 ]
 
 
@@ -97,3 +99,20 @@ def test_noalloc_rejects_what_does_not_fit(ns):
     ref = ns.ns_eval_ex(A, 81, "radix9", "f64")
     torch.cuda.synchronize()
     assert torch.equal(got, ref)
+
+
+def test_noalloc_back_to_back_calls_keep_their_own_parameters(ns):
+    """Two calls in a row on one stream with no synchronisation between them:
+    the second call's parameter upload must not reach the array before the
+    first call's kernels have read it (the upload is ordered on the stream),
+    so both results equal the handle path's."""
+    w1 = workloads.symmetric(300, 0.9, 21)
+    w2 = workloads.symmetric(150, 0.5, 22)
+    A1, A2 = to_dev(w1.A, "f64"), to_dev(w2.A, "f64")
+    o1 = torch.empty_like(A1)
+    o2 = torch.empty_like(A2)
+    ns.ns_eval_noalloc(A1, 729, "radix9", "f64", out=o1)
+    ns.ns_eval_noalloc(A2, 81, "binary", "f64", out=o2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, ns.ns_eval_ex(A1, 729, "radix9", "f64"))
+    assert torch.equal(o2, ns.ns_eval_ex(A2, 81, "binary", "f64"))
