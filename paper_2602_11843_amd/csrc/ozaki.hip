@@ -16,18 +16,22 @@
 // the digit remainders bound the error by about n 2^(e_i + f_j) (s + 1) 2^-7s.
 //
 // Layout.  The digits of plane p (p = 0..s-1) form a panel of the n x n int8
-// matrix M (X by rows; Y^T, i.e. Y by columns) with the byte layout of the
-// 16-bit panels of an n x n/2 matrix: 16 x 64-byte blocks of 1 KB, block (rb,
-// kb) at byte (kb (n/16) + rb) 1024, row rr's 16-byte chunk c at rr 64 +
-// 16 (c ^ swz(rr)).  So the product kernel's loader and fragment reads are
-// the 16-bit panel kernel's, in 16-bit units.
+// matrix M (X by rows; Y^T, i.e. Y by columns).  X's planes have the byte
+// layout of the 16-bit panels of an n x n/2 matrix: 16 x 64-byte blocks of
+// 1 KB, block (rb, kb) at byte (kb (n/16) + rb) 1024, row rr's 16-byte chunk c
+// at rr 64 + 16 (c ^ swz(rr)).  Y's planes are fragment-major: one 1 KB unit
+// per (32-row group g, 64-byte slab kb, 32-byte step ks), unit
+// (kb (n/32) + g) 2 + ks, lane l's 16 bytes at 16 l holding row 32 g + (l & 31),
+// k = 64 kb + 32 ks + 16 (l >> 5) .. + 15 -- one MFMA B operand.  So the product
+// kernel's X loader and fragment reads are the 16-bit panel kernel's, in
+// 16-bit units, and its waves load Y straight into registers (ydirect.h).
 //
 // Product.  One launch per diagonal, d = s + 1 down to 2, each over K = (d - 1) n:
 // k-chunk c reads X plane j = c / (n/64) and Y plane d - 2 - j.  The launch of
 // the last diagonal adds the FP64 partial sum of the earlier ones, scales by
 // 2^(e_i + f_j) and applies the product's affine epilogue; the others write
 // their partial sum (FP64) to an accumulator matrix.
-#include "gemm_device.h"
+#include "ydirect.h"
 
 namespace ns {
 namespace dev {
@@ -101,8 +105,22 @@ __global__ __launch_bounds__(256) void slices_kernel(const double* __restrict__ 
     }
   }
   __syncthreads();
-  const int blk = tid >> 6, pos = tid & 63, rr = pos >> 2, pc = pos & 3;
-  const int r = 16 * blk + rr, kk = 16 * (pc ^ swz8(rr));
+  // each thread: 16 consecutive k of one row of M, written as one 16-byte
+  // chunk per plane -- by rows (X) one chunk of the swizzled blocks, by
+  // columns (Y) one lane's share of a fragment-major unit
+  int r, kk;
+  size_t off;
+  if (!transpose) {
+    const int blk = tid >> 6, pos = tid & 63, rr = pos >> 2, pc = pos & 3;
+    r = 16 * blk + rr;
+    kk = 16 * (pc ^ swz8(rr));
+    off = ((size_t)(k0 / 64) * (n / 16) + (r0 / 16 + blk)) * 1024 + 16 * pos;
+  } else {
+    const int u = tid >> 6, l = tid & 63, gl = u & 1, ks = u >> 1;
+    r = 32 * gl + (l & 31);
+    kk = 32 * ks + 16 * (l >> 5);
+    off = (((size_t)(k0 / 64) * (n / 32) + (r0 / 32 + gl)) * 2 + ks) * 1024 + 16 * l;
+  }
   const int e = exp_above(mx[r0 + r]);
   double x[16];
 #pragma unroll
@@ -111,7 +129,6 @@ __global__ __launch_bounds__(256) void slices_kernel(const double* __restrict__ 
     x[i] = (v == v && fabs(v) < 1.0) ? v : 0.0;   // non-finite rows are flagged by the product
   }
   const size_t plane = (size_t)n * n;
-  const size_t off = ((size_t)(k0 / 64) * (n / 16) + (r0 / 16 + blk)) * 1024 + 16 * pos;
   for (int p = 0; p < s; ++p) {
     i32x4 w;
 #pragma unroll
@@ -143,27 +160,25 @@ struct I8Args {
   const GemmParams* epi;    // the product's epilogue (device), read by the last launch
 };
 
-// 256 x 256 tile, 8 waves of 128 x 64 (4 x 2 fragments of
-// v_mfma_i32_32x32x32_i8), k-chunk 64 int8 (two MFMA steps), two LDS stages.
+// 128 x 256 tile, 4 waves of 128 x 64 (4 x 2 fragments of
+// v_mfma_i32_32x32x32_i8), k-chunk 64 int8 (two MFMA steps), X through LDS
+// (three stages of 8 KB), Y in a ring of D chunks of registers; two
+// workgroups per CU, so one's epilogue (FP64 partial sums) runs beside the
+// other's k-loop.
 struct PolI8 {
-  static constexpr int NWM = 2, NWN = 4, NI = 4, NJ = 2;
+  static constexpr int NWM = 1, NWN = 4, NI = 4, NJ = 2, D = 4, MINB = 2;
   static constexpr int WTM = 32 * NI, WTN = 32 * NJ;
   static constexpr int BM = NWM * WTM, BN = NWN * WTN;
-  static constexpr int BK16 = 32;                    // k-chunk in 16-bit units (64 int8)
   static constexpr int THREADS = 64 * NWM * NWN, NW = THREADS / 64;
-  static constexpr int A_BLK = BM / 16, B_BLK = BN / 16;   // 1 KB blocks per chunk
-  static constexpr int A_EL = A_BLK * 512, STAGE_EL = (A_BLK + B_BLK) * 512;
-  static constexpr int STAGES = 2;
-  static constexpr int PER_WAVE = (A_BLK + B_BLK) / NW;
-  static_assert((A_BLK + B_BLK) % NW == 0, "loader blocks per wave");
   static constexpr int EFR = 2;                      // fragment-rows per epilogue pass
   static constexpr int CPITCH = BN + 4;              // epilogue staging, int32
   static constexpr int EPI_EL = 32 * EFR * CPITCH * 2;
-  static constexpr int SMEM_EL = STAGES * STAGE_EL > EPI_EL ? STAGES * STAGE_EL : EPI_EL;
+  static constexpr int KL_EL = 3 * (BM / 16) * 512;
+  static constexpr int SMEM_EL = KL_EL > EPI_EL ? KL_EL : EPI_EL;
 };
 
 template <class Q>
-__global__ __launch_bounds__(Q::THREADS, 1) void gemm_i8_kernel(const I8Args args) {
+__global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_i8_kernel(const I8Args args) {
   __shared__ __align__(16) uint16_t smem[Q::SMEM_EL];
   const int n = args.n;
   const int tiles_m = n / Q::BM, tiles_n = n / Q::BN;
@@ -173,36 +188,13 @@ __global__ __launch_bounds__(Q::THREADS, 1) void gemm_i8_kernel(const I8Args arg
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / Q::NWN, wn = wave % Q::NWN;
   const size_t plane16 = (size_t)n * n / 2;          // one digit plane, 16-bit units
-  const size_t chunk_el = (size_t)n * Q::BK16;       // one k-chunk of all row blocks
+  const size_t chunk_el = (size_t)n * 32;            // one 64-byte slab of X's row blocks
+  const size_t yslab = (size_t)(n / 32) * 1024;      // one slab of Y's fragment units
   const int nkp = n / 64;                            // k-chunks per plane
   const int nk = (args.d - 1) * nkp;
-
-  uint32_t goff[Q::PER_WAVE];
-  bool isx[Q::PER_WAVE];
-  int loff[Q::PER_WAVE];
-#pragma unroll
-  for (int i = 0; i < Q::PER_WAVE; ++i) {
-    const int b = wave + i * Q::NW;
-    isx[i] = b < Q::A_BLK;
-    goff[i] = isx[i] ? (uint32_t)((row0 / 16 + b) * 512 + 8 * lane)
-                     : (uint32_t)((col0 / 16 + (b - Q::A_BLK)) * 512 + 8 * lane);
-    loff[i] = b * 512;
-  }
-  auto issue = [&](int c, int stage) {
-    const int j = c / nkp, kc = c - j * nkp;
-    const uint16_t* xs = args.X + (size_t)j * plane16 + (size_t)kc * chunk_el;
-    const uint16_t* ys = args.Y + (size_t)(args.d - 2 - j) * plane16 + (size_t)kc * chunk_el;
-#pragma unroll
-    for (int i = 0; i < Q::PER_WAVE; ++i)
-      __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)((isx[i] ? xs : ys) + goff[i]),
-          (__attribute__((address_space(3))) void*)(smem + stage * Q::STAGE_EL + loff[i]), 16, 0, 0);
-  };
-
-  const int fr = lane & 31, rr = fr & 15;
-  const int lrow = (fr >> 4) * 512 + rr * 32;
-  const int cofs0 = 8 * ((lane >> 5) ^ swz8(rr));
-  const int cofs1 = 8 * ((2 + (lane >> 5)) ^ swz8(rr));
+  const uint16_t* const X = args.X;
+  const uint16_t* const Yw = args.Y + (size_t)((col0 + wn * Q::WTN) / 32) * 1024 + 8 * lane;
+  const int d2 = args.d - 2;
 
   i32x16 acc[Q::NI][Q::NJ];
 #pragma unroll
@@ -210,36 +202,20 @@ __global__ __launch_bounds__(Q::THREADS, 1) void gemm_i8_kernel(const I8Args arg
 #pragma unroll
     for (int j = 0; j < Q::NJ; ++j) acc[i][j] = i32x16{};
 
-  issue(0, 0);
-  wait_vmcnt<0>();
-  __syncthreads();
-  int cur = 0;
-  for (int kc = 0; kc < nk; ++kc) {
-    if (kc + 1 < nk) issue(kc + 1, cur ^ 1);
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const uint16_t* As = smem + cur * Q::STAGE_EL;
-      const uint16_t* Bs = As + Q::A_EL;
-      const int co = ks ? cofs1 : cofs0;
-      i32x4 a[Q::NI], b[Q::NJ];
-#pragma unroll
-      for (int i = 0; i < Q::NI; ++i)
-        a[i] = *reinterpret_cast<const i32x4*>(As + (wm * Q::WTM / 16 + 2 * i) * 512 + lrow + co);
-#pragma unroll
-      for (int j = 0; j < Q::NJ; ++j)
-        b[j] = *reinterpret_cast<const i32x4*>(Bs + (wn * Q::WTN / 16 + 2 * j) * 512 + lrow + co);
-#pragma unroll
-      for (int i = 0; i < Q::NI; ++i)
-#pragma unroll
-        for (int j = 0; j < Q::NJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    // chunk kc + 1 in LDS and every wave done with chunk kc before the next
-    // iteration overwrites this stage
-    wait_vmcnt<0>();
-    __syncthreads();
-    cur ^= 1;
-  }
+  // chunk c: X plane j = c / nkp with Y plane d - 2 - j, slab c - j nkp of both
+  kloop_ydirect<Q>(
+      [=](int c) {
+        const int j = c / nkp;
+        return X + (size_t)j * plane16 + (size_t)(c - j * nkp) * chunk_el;
+      },
+      [=](int c) {
+        const int j = c / nkp;
+        return Yw + (size_t)(d2 - j) * plane16 + (size_t)(c - j * nkp) * yslab;
+      },
+      nk, row0, lane, wave, wm, smem, acc, [](i32x16& a, const u16x8& x, const u16x8& y) {
+        a = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4, x), __builtin_bit_cast(i32x4, y), a,
+                                                  0, 0, 0);
+      });
 
   // epilogue: stage EFR fragment-rows of int32 results at a time; each thread
   // then handles row-contiguous vectors of 4
@@ -300,7 +276,7 @@ __global__ __launch_bounds__(Q::THREADS, 1) void gemm_i8_kernel(const I8Args arg
 }  // namespace
 }  // namespace dev
 
-int i8_tile() { return dev::PolI8::BM; }
+int i8_tile() { return dev::PolI8::BN; }    // BN = 256 is a multiple of BM = 128
 
 hipError_t launch_maxabs_rc(const double* src, int n, unsigned long long* rowmax,
                             unsigned long long* colmax, hipStream_t s) {
@@ -323,6 +299,7 @@ hipError_t launch_gemm_i8(const void* xs, const void* ys, int n, int slices, dou
                           const GemmParams* epi, hipStream_t s) {
   using Q = dev::PolI8;
   if (n % Q::BM || n % Q::BN || slices < 1 || slices > kMaxI8Slices) return hipErrorInvalidValue;
+  if ((n / 64) % Q::D) return hipErrorInvalidValue;   // k-chunks per plane: a whole number of ring turns
   const int grid = (n / Q::BM) * (n / Q::BN);
   for (int d = slices + 1; d >= 2; --d) {
     const dev::I8Args a{static_cast<const uint16_t*>(xs), static_cast<const uint16_t*>(ys), n, d,

@@ -31,10 +31,7 @@
 // 512 times that index; lane l's 16 bytes at 8 l hold row 32 g + (l & 31),
 // k = 32 kb + 16 ks + 8 (l >> 5) .. + 7 -- exactly the B operand of one
 // v_mfma_f32_32x32x16_f16, so one wave load is 1 KB contiguous.
-#include <type_traits>
-#include <utility>
-
-#include "gemm_device.h"
+#include "ydirect.h"
 
 namespace ns {
 namespace dev {
@@ -149,144 +146,12 @@ struct PolPanel {
   static constexpr int STAGE_EL = KSLAB * SLAB_EL;
   static constexpr int PER_WAVE = KSLAB * (A_BLK + B_BLK) / NW;
   static_assert((KSLAB * (A_BLK + B_BLK)) % NW == 0, "loader blocks per wave");
-  static constexpr int XSTAGE_EL = BM / 16 * 512;             // direct Y: one X chunk
-  static constexpr int X_PER_WAVE = BM / 16 / NW;
-  static_assert(!YDIR || (BM / 16) % NW == 0, "X loader blocks per wave");
-  static constexpr int KL_EL = YDIR ? 3 * XSTAGE_EL : STAGES * STAGE_EL;
+  static constexpr int KL_EL = YDIR ? 3 * (BM / 16) * 512 : STAGES * STAGE_EL;   // direct Y: three X chunks
   static constexpr int CPITCH = BN + 4;                       // epilogue staging, floats
   static constexpr int EPI_EL = 32 * EFR * CPITCH * 2;       // one pass, in 16-bit units
   static constexpr int SMEM_EL = KL_EL > EPI_EL ? KL_EL : EPI_EL;
 };
 
-// s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt bits 3:0 and 15:14,
-// expcnt 6:4 left at its maximum, lgkmcnt 11:8 zero)
-template <int N>
-__device__ __forceinline__ void wait_vm_lgkm0() {
-  static_assert(N >= 0 && N < 64, "vmcnt immediate");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0070);
-}
-
-// Workgroup barrier without a memory fence.  The fence of __syncthreads would
-// wait for every outstanding load, the register ring's included; the callers
-// wait for the LDS traffic and the X chunk they need themselves (above), and
-// the empty asm statements keep the compiler from moving memory accesses
-// across the barrier.
-__device__ __forceinline__ void bare_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// f(integral_constant<int, U>) for U = 0, 1, ... in order (ring slots must be
-// compile-time indices to stay in registers)
-template <class F, int... U>
-__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, U...>) {
-  (f(std::integral_constant<int, U>{}), ...);
-}
-
-// Re-defines ring registers whose loads the waits have completed, so that the
-// compiler carries no pending load for them over the loop's back edge (it
-// would otherwise wait for every load at the head of the loop).
-template <int A, int B>
-__device__ __forceinline__ void settle(u16x8 (&r)[A][B]) {
-#pragma unroll
-  for (int a = 0; a < A; ++a)
-#pragma unroll
-    for (int b = 0; b < B; ++b) asm volatile("" : "+v"(r[a][b]));
-}
-
-// k-loop with Y in registers: X chunk kc + 2 is copied into LDS (direct-to-LDS,
-// three stages) while chunk kc is multiplied; Y chunk kc + D is loaded into the
-// ring slot chunk kc has just used.  At the end of iteration kc every load up
-// to X chunk kc + 1 has landed (the newest two Y chunks and X chunk kc + 2 may
-// fly), so a Y chunk has two iterations to arrive.  n / 32 is a multiple of D
-// and at least 2 D (checked by the launcher).
-template <class Q>
-__device__ __forceinline__ void kloop_ydirect(const uint16_t* __restrict__ Xp,
-                                              const uint16_t* __restrict__ Yf, int n, int row0,
-                                              int col0, int lane, int wave, int wm, int wn,
-                                              uint16_t* smem, f32x16 (&acc)[Q::NI][Q::NJ]) {
-  constexpr int D = Q::D, PW = Q::X_PER_WAVE, YOPS = 2 * Q::NJ;
-  static_assert(2 * YOPS + PW < 64 && (D - 1) * YOPS < 64, "vmcnt range");
-  uint32_t goff[PW];
-  int loff[PW];
-#pragma unroll
-  for (int i = 0; i < PW; ++i) {
-    const int b = wave + i * Q::NW;
-    goff[i] = (uint32_t)((row0 / 16 + b) * 512 + 8 * lane);
-    loff[i] = b * 512;
-  }
-  const size_t chunk_el = (size_t)n * 32;
-  auto issue = [&](int kc, int stage) {
-    const uint16_t* src = Xp + (size_t)kc * chunk_el;
-#pragma unroll
-    for (int i = 0; i < PW; ++i)
-      __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)(src + goff[i]),
-          (__attribute__((address_space(3))) void*)(smem + stage * Q::XSTAGE_EL + loff[i]), 16, 0, 0);
-  };
-  const uint16_t* ybase = Yf + (size_t)((col0 + wn * Q::WTN) / 32) * 1024 + 8 * lane;
-  const size_t yslab = (size_t)(n / 32) * 1024;
-  auto yload = [&](int kc, u16x8 (&dst)[2][Q::NJ]) {
-    const uint16_t* src = ybase + (size_t)kc * yslab;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-      for (int j = 0; j < Q::NJ; ++j)
-        dst[ks][j] = *reinterpret_cast<const u16x8*>(src + j * 1024 + ks * 512);
-  };
-  // X fragment reads as in the LDS k-loop
-  const int fr = lane & 31, rr = fr & 15;
-  const int lrow = (fr >> 4) * 512 + rr * 32;
-  const int cofs0 = 8 * ((lane >> 5) ^ swz(rr));
-  const int cofs1 = 8 * ((2 + (lane >> 5)) ^ swz(rr));
-  const int nk = n / 32;
-  u16x8 yb[D][2][Q::NJ];
-  issue(0, 0);
-  issue(1, 1);
-#pragma unroll
-  for (int c = 0; c < D; ++c) yload(c, yb[c]);
-  wait_vm_lgkm0<(D - 1) * YOPS>();          // X chunks 0 and 1 and ring slot 0 landed
-  settle(yb[0]);
-  bare_barrier();
-  int cur = 0;
-  auto step = [&](int k, u16x8 (&ybu)[2][Q::NJ], auto steady) {
-    constexpr bool ST = decltype(steady)::value;
-    if (ST || k + 2 < nk) issue(k + 2, cur == 0 ? 2 : cur - 1);
-    const uint16_t* As = smem + cur * Q::XSTAGE_EL;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const int co = ks ? cofs1 : cofs0;
-      u16x8 ah[Q::NI];
-#pragma unroll
-      for (int i = 0; i < Q::NI; ++i)
-        ah[i] = *reinterpret_cast<const u16x8*>(As + (wm * Q::WTM / 16 + 2 * i) * 512 + lrow + co);
-#pragma unroll
-      for (int i = 0; i < Q::NI; ++i)
-#pragma unroll
-        for (int j = 0; j < Q::NJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, ah[i]),
-                                                             __builtin_bit_cast(f16x8, ybu[ks][j]),
-                                                             acc[i][j], 0, 0, 0);
-    }
-    if constexpr (ST) {
-      yload(k + D, ybu);
-      wait_vm_lgkm0<2 * YOPS + PW>();
-    } else {
-      wait_vm_lgkm0<0>();
-    }
-    bare_barrier();
-    cur = cur == 2 ? 0 : cur + 1;
-  };
-  int kc = 0;
-  for (; kc + 2 * D <= nk; kc += D) {
-    unroll_seq([&](auto u) { step(kc + u, yb[u], std::true_type{}); },
-               std::make_integer_sequence<int, D>{});
-    settle(yb[0]);
-  }
-  unroll_seq([&](auto u) { step(kc + u, yb[u], std::false_type{}); },   // the last D chunks
-             std::make_integer_sequence<int, D>{});
-}
 
 template <class Q>
 __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_panel_kernel(const MainArgs args) {
@@ -308,7 +173,14 @@ __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_panel_kernel(const M
     for (int j = 0; j < Q::NJ; ++j) acc[i][j] = f32x16{};
 
   if constexpr (Q::YDIR) {
-    kloop_ydirect<Q>(Xp, Yp, n, row0, col0, lane, wave, wm, wn, smem, acc);
+    const size_t chunk_el = (size_t)n * 32, yslab = (size_t)(n / 32) * 1024;
+    const uint16_t* ybase = Yp + (size_t)((col0 + wn * Q::WTN) / 32) * 1024 + 8 * lane;
+    kloop_ydirect<Q>([=](int c) { return Xp + (size_t)c * chunk_el; },
+                     [=](int c) { return ybase + (size_t)c * yslab; }, n / 32, row0, lane, wave, wm,
+                     smem, acc, [](f32x16& a, const u16x8& x, const u16x8& y) {
+                       a = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, x),
+                                                                  __builtin_bit_cast(f16x8, y), a, 0, 0, 0);
+                     });
   } else {
   const size_t plane = (size_t)n * n;
   const size_t chunk_el = (size_t)n * Q::BK;      // one k-chunk: KSLAB slabs of n/16 blocks
@@ -507,7 +379,7 @@ using H16Panel = PolPanel<1, 4, 4, 2, false, 1, 2, 2, 2, true, true, 4>;
 template <class Q>
 hipError_t launch_panel(const GemmParams& host, const GemmParams* dev, hipStream_t s) {
   if (host.n % Q::BM || host.n % Q::BN || host.ld != host.n) return hipErrorInvalidValue;
-  if (Q::YDIR && ((host.n / 32) % Q::D || host.n / 32 < 2 * Q::D)) return hipErrorInvalidValue;
+  if (Q::YDIR && ((host.n / 32) % Q::D || host.n / 32 < Q::D)) return hipErrorInvalidValue;
   const int grid = (host.n / Q::BM) * (host.n / Q::BN);
   const MainArgs a{host.X, host.Y, host.n, host.ld, dev, nullptr, nullptr, nullptr, grid};
   hipLaunchKernelGGL(gemm_panel_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
