@@ -25,7 +25,8 @@ Workloads (n is the matrix dimension, k the series length):
                     detection as an application); no channel data is used.
 
 The same construction at any other n is available for tests (``symmetric``,
-``gaussian``, ``jacobi``).
+``gaussian``, ``jacobi``), and ``dyadic`` builds sparse inputs whose low
+powers are exact in every floating-point format the library computes in.
 """
 
 from dataclasses import dataclass, field
@@ -53,6 +54,23 @@ def symmetric(n: int, lam_max: float, seed: int) -> SymmetricInput:
     A = (Q * lam) @ Q.T
     A = 0.5 * (A + A.T)
     return SymmetricInput(A=A, Q=Q, lam=lam, seed=seed)
+
+
+def dyadic(n: int, seed: int, terms: int = 3) -> np.ndarray:
+    """A = (1/8) sum_t diag(s_t) P_t: ``terms`` random permutation matrices
+    P_t with random row signs s_t = +-1.  Every entry is a multiple of 1/8 of
+    magnitude at most terms/8, each row and column has at most ``terms``
+    nonzeros, so ||A||_inf <= terms/8 and low powers of A stay on a coarse
+    dyadic grid (A^j: multiples of 8^-j, at most terms^j of them per entry).
+    A test input on which floating-point arithmetic of a few powers is exact."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    rows = np.arange(n)
+    for _ in range(terms):
+        perm = rng.permutation(n)
+        sign = rng.choice([-1.0, 1.0], size=n)
+        np.add.at(A, (rows, perm), sign / 8.0)
+    return A
 
 
 def power_iteration_radius(G: np.ndarray, seed: int, iters: int = 400,
