@@ -109,7 +109,7 @@ def kernel_name(engine, n):
                 else "gemm_lowp_kernel<PolLow<2,2,1,1,true>>")
     if engine == "i8":
         return "gemm_i8_kernel<PolI8> (one launch per slice diagonal)"
-    return ("gemm_panel_kernel<PolPanel<1,4,4,2,false,...,Y in registers>>" if n >= 2560
+    return ("gemm_panel_kernel<PolPanel<1,4,4,2,false,...,Y in registers>>" if n >= 1792
             else "gemm_lowp_kernel<PolLow<2,2,1,1,false>>")
 
 

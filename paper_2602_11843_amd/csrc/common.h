@@ -70,13 +70,15 @@ int gemm_grid(Engine e, int n);
 // Low-precision products at large n (panel.hip): each operand is first
 // rewritten into 16-bit panels (bf16 hi/lo planes, or one scaled fp16 plane),
 // X by rows and Y by columns, then multiplied from the panels.
-// n from which each 16-bit engine multiplies from panels (and pads to its
-// 256 x 256 tile); below it the operands are converted in the k-loop of a
+// n from which each 16-bit engine multiplies from panels (and pads to a
+// multiple of 256); below it the operands are converted in the k-loop of a
 // 64 x 64 tile, which keeps more CUs busy.  Measured on radix-9, k = 81
-// (panels against in-loop conversion, whole call): split-BF16 1.92 against
-// 1.12 ms at n = 2048, 2.39 against 2.02 at 2560, 2.93 against 3.13 at
-// 3072; scaled FP16 1.38 against 1.26 ms at 2048, 1.61 against 2.05 at 2560.
-constexpr int kPanelMinBF16X3 = 3072, kPanelMinF16S = 2560;
+// (panels against in-loop conversion, whole call): split-BF16 (256 x 256
+// tiles) 1.93 against 1.03 ms at n = 2048, 2.39 against 1.96 at 2560, 2.89
+// against 2.88 at 3072; scaled FP16 (128 x 256 tiles, two per CU) 1.00
+// against 0.73 ms at 1536, 1.04 against 1.18 at 1792, 1.10 against 1.34 at
+// 2048.
+constexpr int kPanelMinBF16X3 = 3072, kPanelMinF16S = 1792;
 inline int panel_min(Engine e) { return e == ENG_BF16X3 ? kPanelMinBF16X3 : kPanelMinF16S; }
 bool panel_path(Engine e, int n);
 size_t panel_bytes(Engine e, int n);      // bytes of one operand's panels

@@ -44,7 +44,8 @@ def test_kernel_names_follow_the_tile_thresholds():
     assert bench.kernel_name("f32", 8192) == "gemm_kernel<PolF32<2,2,4,8>>"
     assert bench.kernel_name("f32", 2048) == "gemm_kernel<PolF32<2,2,2,2>>"
     assert "PolPanel" in bench.kernel_name("split_bf16", 8192)
-    assert "PolLow" in bench.kernel_name("f16_scaled", 2048)
+    assert "PolLow" in bench.kernel_name("f16_scaled", 1536)
+    assert "PolPanel" in bench.kernel_name("f16_scaled", 2048)
 
 
 def _fake_root(tmp_path, traffic=123456789):

@@ -54,7 +54,7 @@ def case(n):
 
 
 DTYPES = ["f64", "f32", "f32_acc64", "split_bf16", "f16_scaled"]
-# padded sizes of the panel paths (multiples of 256 from n = 2560 for FP16 and
+# padded sizes of the panel paths (multiples of 256 from n = 1792 for FP16 and
 # n = 3072 for split-BF16)
 PANEL = {(2600, "f16_scaled"): 2816, (3072, "f16_scaled"): 3072, (3072, "split_bf16"): 3072}
 

@@ -108,13 +108,16 @@ def test_mixed_any_k_precision_forms(ns, dtype, n):
         assert rep["gemms_performed"] == orep["products"] and rep["k_eff"] == k
 
 
-@pytest.mark.parametrize("dtype", ["split_bf16", "f16_scaled"])
-@pytest.mark.parametrize("n,n_internal", [(2100, 2176), (3100, 3328)])
+@pytest.mark.parametrize("dtype,n,n_internal", [
+    ("split_bf16", 2100, 2176), ("split_bf16", 3100, 3328),
+    ("f16_scaled", 1700, 1728), ("f16_scaled", 2100, 2304)])
 def test_low_precision_padding(ns, dtype, n, n_internal):
-    """Padded matrices on both 16-bit paths: n = 2100 converts in the k-loop
-    (64-wide tiles, padded to the FP64 tile, 2176); n = 3100 runs from panels
-    (256-wide tiles, 3328).  The padding block must stay exactly zero through
-    every product."""
+    """Padded matrices on both paths of each 16-bit form: below its panel
+    threshold (split-BF16 3072, FP16 1792) the operands are converted in the
+    k-loop (64-wide tiles, padded to the larger of 64 and the FP64 tile:
+    2176 at 2100, 1728 at 1700); from it the products run from panels
+    (256-wide padding: 3328, 2304).  The padding block must stay exactly zero
+    through every product."""
     w = workloads.symmetric(n, 0.9, 31)
     got, rep = run(ns, w.A, 81, "radix9", dtype)
     assert rep["n_internal"] == n_internal
