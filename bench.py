@@ -40,6 +40,7 @@ product launch on the call's stream, per product engine.  The CPU oracle
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import tempfile
@@ -296,6 +297,18 @@ def close(got, ref):
             float(np.max(np.abs(d)) / np.max(np.abs(ref))))
 
 
+def residual_fro(torch, A, S):
+    """||I - (I - A) S||_F, the accuracy measure of Sec. 6, in FP64 from the
+    call's input A and output S (device or host tensors).  A check of the
+    result, computed with torch.matmul outside the timed region."""
+    A64, S64 = A.double(), S.double()
+    R = S64 - torch.matmul(A64, S64)
+    R.diagonal().sub_(1.0)
+    v = float(torch.linalg.norm(R))
+    del R, A64, S64
+    return v if math.isfinite(v) else None
+
+
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
@@ -334,7 +347,9 @@ def bench_precision_sym(args, torch, ns):
             r["rel_err_vs_definition"], r["max_elem_err_vs_definition"] = close(
                 got, ref_bin if method == "binary" else ref)
             del got
-            log(f"[bench]   rel err vs FP64 definition {r['rel_err_vs_definition']:.3e}")
+            r["residual_fro"] = residual_fro(torch, A, out)
+            log(f"[bench]   rel err vs FP64 definition {r['rel_err_vs_definition']:.3e}, "
+                f"||I - (I - A) S||_F {r['residual_fro']:.3e}")
         res[f"{method}:{dtype}"] = r
     cpu = None
     if not args.no_cpu_baseline:
@@ -393,6 +408,7 @@ def bench_gaussian_rho(args, torch, ns):
                 got = o[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
                 r["rel_err_sampled_vs_inverse"], r["max_elem_err_sampled_vs_inverse"] = close(
                     got, refs["f32" if dtype == "f32" else "f64"])
+                r["residual_fro"] = residual_fro(torch, Ad, o)
                 log(f"[bench]   rho {rho} {method} {dtype}: sampled rel err vs (I-A)^-1 "
                     f"{r['rel_err_sampled_vs_inverse']:.3e}, level norms "
                     f"{['%.3g' % x for x in r['level_norm']]}")
@@ -426,6 +442,7 @@ def bench_large_symmetric(args, torch, ns):
             got = out[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
             ref = series.spectral_form(w.Q, w.lam, r["k_eff"], cols=cols)
             r["rel_err_sampled_vs_definition"], _ = close(got, ref)
+            r["residual_fro"] = residual_fro(torch, A, out)
         res[f"{method}:{dtype}"] = r
     h.close()
     info = {"workload": "large_symmetric", "n": n, "k": k, "seed": w.seed, "lam": "U[-0.95,0.95]"}
@@ -530,6 +547,7 @@ def bench_small_symmetric(args, torch, ns):
         if not args.no_check:
             r["rel_err_vs_closed_form"], _ = close(out.cpu().numpy(),
                                                    series.spectral_form(w.Q, w.lam, r["k_eff"]))
+            r["residual_fro"] = residual_fro(torch, A, out)
         res[f"{method}:{dtype}"] = r
     cpu = None
     if not args.no_cpu_baseline:

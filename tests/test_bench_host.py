@@ -1,6 +1,6 @@
 """Host-side checks of the benchmark's measurement logic (no GPU): the
 per-launch roofline arithmetic, the counter-traffic lookup and its source
-hash, the CPU sample loop, and the one-GPU guard."""
+hash, the CPU sample loop, the one-GPU guard and the residual measure."""
 
 import hashlib
 import os
@@ -8,6 +8,7 @@ import shutil
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -95,3 +96,19 @@ def test_rounding_keeps_small_errors_visible():
     r = bench.rnd({"err": 4.643212e-15, "ms": 244.13781234, "nested": {"e": 7.5881e-11}})
     assert r["err"] == 4.643212e-15 and r["nested"]["e"] == 7.5881e-11
     assert r["ms"] == 244.1378
+
+
+def test_residual_measure_matches_closed_form():
+    """||I - (I - A) S||_F for S = S_k(A) is ||A^k||_F: on a diagonal A with
+    entries lam, sqrt(sum lam^(2k)).  Host tensors, FP64."""
+    torch = pytest.importorskip("torch")
+    lam = np.array([0.5, -0.25, 0.75, 0.0, 0.125])
+    k = 9
+    A = torch.from_numpy(np.diag(lam))
+    S = torch.from_numpy(np.diag((1 - lam ** k) / (1 - lam)))
+    want = float(np.sqrt(np.sum(lam ** (2 * k))))
+    assert bench.residual_fro(torch, A, S) == pytest.approx(want, rel=1e-12)
+    # FP32 inputs are widened, and a non-finite result is reported as None
+    assert bench.residual_fro(torch, A.float(), S.float()) == pytest.approx(want, rel=1e-6)
+    S[0, 0] = float("inf")
+    assert bench.residual_fro(torch, A, S) is None
