@@ -645,7 +645,7 @@ def build_line(args, name, res, cpu, info):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         return 2
     import torch

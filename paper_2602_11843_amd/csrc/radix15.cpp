@@ -144,7 +144,7 @@ Table build(const double* start) {
   Table t{};
   R x[NP];
   for (int p = 0; p < NP; ++p) x[p] = start[p];
-  // heap scratch (about 55 KB), private to this build
+  // heap scratch (about 55 KB), private to this call
   std::vector<DPoly> scratch(7);
   DPoly* basis = scratch.data();
   DPoly& T = scratch[6];
