@@ -66,3 +66,81 @@ def test_operands_fit_in_eight_bits():
     A2 = A @ A
     for M in (I + A, A, A2, A2 @ A2):
         assert max(significant_bits(v) for v in M.ravel()) <= 8
+
+
+def exact_sk_cyclic(A, k):
+    """S_k(A) = sum_{j<k} A^j in Fractions for A = scale * signed n-cycle,
+    composing the cycle exactly (no floating point)."""
+    n = A.shape[0]
+    col = [int(np.flatnonzero(A[i])[0]) for i in range(n)]
+    val = [Fraction(float(A[i, col[i]])) for i in range(n)]
+    S = [dict() for _ in range(n)]
+    for i in range(n):
+        pos, coef = i, Fraction(1)
+        for _ in range(k):
+            S[i][pos] = S[i].get(pos, Fraction(0)) + coef
+            coef *= val[pos]
+            pos = col[pos]
+    return S
+
+
+# the schedules with dyadic weights, at the lengths the bit-for-bit GPU tests
+# use (the any-k plans for 30 and 75 take radices 2, 3 and 5 only).  Radix-15
+# approximates T_15, and the radix-9 kernel's weights 3/20, 11/40 and 767/800
+# round in binary, so neither is exact here.
+CYCLIC_CASES = [("binary", 32), ("naive", 16), ("hensel", 32), ("ternary", 27), ("quinary", 25),
+                ("mixed", 30), ("mixed", 75)]
+
+
+def test_cyclic_mixed_plans_avoid_radix9():
+    assert 9 not in series.mixed_plan(30)[1] and 9 not in series.mixed_plan(75)[1]
+
+
+@pytest.mark.parametrize("method,k", CYCLIC_CASES)
+def test_oracle_exact_on_cyclic_inputs(method, k):
+    """On a scaled signed n-cycle the powers A^j (j < n) occupy disjoint
+    positions, each entry a signed power of 1/2: the oracle's FP64 schedule
+    must equal the exact S_k entry for entry (n = 96 > k)."""
+    n = 96
+    A = workloads.cyclic(n, 7)
+    got, rep = series.evaluate(A, k, method)
+    assert rep["k_eff"] == k
+    S = exact_sk_cyclic(A, k)
+    for i in range(n):
+        for j in range(n):
+            assert Fraction(float(got[i][j])) == S[i].get(j, 0), (method, i, j)
+
+
+def test_cyclic_closed_form_helper():
+    """The vectorised closed form the GPU tests compare with equals the
+    Fraction composition."""
+    A = workloads.cyclic(64, 9)
+    S = exact_sk_cyclic(A, 40)
+    ref = sk_signed_cycle(A, 40)
+    assert all(Fraction(float(ref[i, j])) == S[i].get(j, 0) for i in range(64) for j in range(64))
+
+
+def sk_signed_cycle(A, k):
+    """S_k(A) for A with one nonzero per row (a scaled signed permutation),
+    by walking the permutation: row i of A^j is A^(j-1)'s row i moved one
+    step along the cycle and scaled by the entry there (FP64; exact while
+    every power is a signed power of two at its own position)."""
+    n = A.shape[0]
+    col = np.argmax(A != 0, axis=1)
+    val = A[np.arange(n), col]
+    S = np.zeros((n, n))
+    rows, pos, coef = np.arange(n), np.arange(n), np.ones(n)
+    for _ in range(k):
+        S[rows, pos] += coef
+        coef = coef * val[pos]
+        pos = col[pos]
+    return S
+
+
+def test_cyclic_powers_are_single_bits():
+    A = workloads.cyclic(200, 3)
+    P = np.eye(200)
+    for j in range(1, 30):
+        P = P @ A
+        nz = P[P != 0]
+        assert nz.size == 200 and np.all(np.abs(nz) == 0.5 ** j)

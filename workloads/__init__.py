@@ -73,6 +73,21 @@ def dyadic(n: int, seed: int, terms: int = 3) -> np.ndarray:
     return A
 
 
+def cyclic(n: int, seed: int, scale: float = 0.5) -> np.ndarray:
+    """A = scale * diag(s) P for P the permutation matrix of one random
+    n-cycle and s random signs.  A^j is then scale^j times a signed
+    permutation whose nonzeros sit where those of A^i (i < n, i != j) do
+    not, so every power, and every sum of distinct powers, has one entry per
+    row and column that is a signed power of ``scale``."""
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n)
+    nxt = np.empty(n, dtype=np.int64)
+    nxt[order] = np.roll(order, -1)               # one cycle through all of 0..n-1
+    A = np.zeros((n, n))
+    A[np.arange(n), nxt] = rng.choice([-1.0, 1.0], size=n) * scale
+    return A
+
+
 def power_iteration_radius(G: np.ndarray, seed: int, iters: int = 400,
                            tail: int = 200) -> float:
     """Spectral-radius estimate: ``iters`` power iterations from a seeded
