@@ -23,8 +23,8 @@ of Y needs at most 7 s bits (Hensel at k = 32 needs 16).
 
 References: the oracle at n = 300; the closed form ``sk_signed_cycle``
 (pinned to exact rationals and to the oracle in ``test_dyadic_exact.py``) at
-the panel and large-tile sizes, where the oracle's FP64 products would take
-the test past a minute.
+the panel, large-tile and full (n = 8192) sizes, where the oracle's FP64
+products would take the test past a minute.
 """
 
 import sys
@@ -121,7 +121,26 @@ def test_large_tiles_equal_closed_form(ns, n, method, k, k16, dtypes):
             assert rep["n_internal"] == PANEL[(n, dtype)]
 
 
-@pytest.mark.parametrize("n", [300, 3072])
+@pytest.mark.parametrize("method,k,k16", [("binary", 64, 32), ("ternary", 27, 27)])
+def test_full_size_exact(ns, method, k, k16):
+    """n = 8192, the size of the precision-form and large FP32 workloads: every
+    engine in the launch configuration those workloads time (FP64 128 x 128
+    and FP32 128 x 256 tiles, both 16-bit panel products), bit for bit."""
+    n = 8192
+    A = cyc(n)
+    refs = {}
+    for dtype in ALL:
+        kk = k16 if dtype == "f16_scaled" else k
+        if kk not in refs:
+            refs[kk] = sk_signed_cycle(A, kk)
+        say(f"[gpu] exact cyclic {method} k={kk} {dtype} n={n}")
+        got, rep = run(ns, A, kk, method, dtype)
+        check(got, refs[kk], method, dtype, kk, n)
+        assert rep["n_internal"] == n
+        del got
+
+
+@pytest.mark.parametrize("n", [300, 3072, 8192])
 @pytest.mark.parametrize("dtype", ["f32_acc64+i8", "split_bf16+i8+last", "f16_scaled+i8x6"])
 def test_int8_residual_exact_cyclic(ns, n, dtype):
     """Hensel at k = 32 with the int8-emulated residual: A's rows need one
