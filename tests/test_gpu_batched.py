@@ -76,6 +76,28 @@ def test_batched_matches_oracle(ns, method):
     assert rep["gemms_performed"] == ns.ns_plan(k, method)[2]
 
 
+@pytest.mark.parametrize("method", ["binary", "naive"])
+def test_batched_exact_on_signed_cycles(ns, method):
+    """Every matrix a scaled signed n-cycle (workloads.cyclic): at k = 16 each
+    entry of every operand and product is a sum of signed powers 2^-j,
+    j <= 16, so the FP32 batched kernel is exact and must equal S_16 in every
+    element, for every n the tile shapes meet (n = 1 .. 3 wrap the cycle
+    around, which keeps the sums within 17 bits)."""
+    from test_dyadic_exact import sk_signed_cycle
+    rng = np.random.default_rng(5)
+    sizes = [1, 2, 3, 8, 13, 16, 32, 50, 64, 65, 100, 128, 129, 200, 255, 256] * 2
+    rng.shuffle(sizes)
+    mats = [workloads.cyclic(int(n), 900 + i) for i, n in enumerate(sizes)]
+    A, offd, nd, nh, offs, ns_ = device_batch(mats)
+    say(f"[gpu] batched exact signed cycles {method} batch={len(mats)} k=16")
+    out = ns.ns_eval_batched(A, offd, nd, nh, 16, method, "f32")
+    torch.cuda.synchronize()
+    got = unpack(out.cpu().numpy(), offs, ns_)
+    for M, G in zip(mats, got):
+        ref = sk_signed_cycle(M, 16)
+        assert np.array_equal(G.astype(np.float64), ref), (method, M.shape[0])
+
+
 def test_batched_bit_identical_to_launch_loop(ns):
     """Same tile arithmetic, same padding: the persistent kernel and the
     per-matrix launch loop must agree bit for bit."""
