@@ -9,10 +9,11 @@
 // so X_ij = 2^e_i (sum_p d_p 2^-7p + r 2^-7s), |r| < 1.  Y is cut the same way
 // by columns (exponents f_j).  Then
 //   (X Y)_ij ~ 2^(e_i + f_j) sum_{p + q <= s + 1} 2^-7(p+q) (D_p E_q)_ij,
-// every D_p E_q an int8 product with int32 accumulation, exact while
-// K 127^2 (s - 1) < 2^31 (K = n up to 16384 for s = 8).  The pairs of one
+// every D_p E_q an int8 product with int32 accumulation.  The pairs of one
 // diagonal d = p + q share their scale, so one diagonal is ONE int8 product
-// over the k-concatenation of its d - 1 slice pairs.  The dropped pairs and
+// over the k-concatenation of its d - 1 slice pairs; the longest (d = s + 1)
+// sums s n products of two digits, exact while s n 127^2 < 2^31 (n up to
+// 16384 for s = 8).  The dropped pairs and
 // the digit remainders bound the error by about n 2^(e_i + f_j) (s + 1) 2^-7s.
 //
 // Layout.  The digits of plane p (p = 0..s-1) form a panel of the n x n int8
