@@ -460,6 +460,27 @@ def spectral_form(Q: np.ndarray, lam: np.ndarray, k: int,
     return (Q * g) @ QT
 
 
+def permutation_form(A: np.ndarray, k: int) -> np.ndarray:
+    """sum_{j<k} A^j (eq. (1)) for A with exactly one nonzero per row (e.g. a
+    scaled signed permutation), term by term without a matrix product: row i
+    of A^j has its one nonzero where row i of A^(j-1) has it, moved along A
+    (column col[pos] of row pos) and scaled by that entry.  FP64; exact while
+    every sum of terms fits in 53 bits."""
+    n = A.shape[0]
+    nz = A != 0
+    if not np.all(nz.sum(axis=1) == 1):
+        raise ValueError("permutation_form needs exactly one nonzero per row")
+    col = np.argmax(nz, axis=1)
+    val = A[np.arange(n), col]
+    S = np.zeros((n, n))
+    rows, pos, coef = np.arange(n), np.arange(n), np.ones(n)
+    for _ in range(k):
+        S[rows, pos] += coef
+        coef = coef * val[pos]
+        pos = col[pos]
+    return S
+
+
 def geometric_sum(x: np.ndarray, k: int) -> np.ndarray:
     """sum_{j<k} x^j for scalars |x| < 1, as (1 - x^k)/(1 - x)."""
     x = np.asarray(x, dtype=np.float64)

@@ -111,30 +111,27 @@ def test_oracle_exact_on_cyclic_inputs(method, k):
             assert Fraction(float(got[i][j])) == S[i].get(j, 0), (method, i, j)
 
 
-def test_cyclic_closed_form_helper():
-    """The vectorised closed form the GPU tests compare with equals the
-    Fraction composition."""
-    A = workloads.cyclic(64, 9)
-    S = exact_sk_cyclic(A, 40)
-    ref = sk_signed_cycle(A, 40)
-    assert all(Fraction(float(ref[i, j])) == S[i].get(j, 0) for i in range(64) for j in range(64))
+@pytest.mark.parametrize("n,k", [(64, 40), (5, 16), (1, 9)])
+def test_permutation_form_is_exact(n, k):
+    """series.permutation_form, the reference of the GPU tests at the large
+    sizes, equals the Fraction composition -- also for cycles shorter than k,
+    where powers wrap onto earlier positions."""
+    A = workloads.cyclic(n, 9)
+    S = exact_sk_cyclic(A, k)
+    ref = series.permutation_form(A, k)
+    assert all(Fraction(float(ref[i, j])) == S[i].get(j, 0) for i in range(n) for j in range(n))
 
 
-def sk_signed_cycle(A, k):
-    """S_k(A) for A with one nonzero per row (a scaled signed permutation),
-    by walking the permutation: row i of A^j is A^(j-1)'s row i moved one
-    step along the cycle and scaled by the entry there (FP64; exact while
-    every power is a signed power of two at its own position)."""
-    n = A.shape[0]
-    col = np.argmax(A != 0, axis=1)
-    val = A[np.arange(n), col]
-    S = np.zeros((n, n))
-    rows, pos, coef = np.arange(n), np.arange(n), np.ones(n)
-    for _ in range(k):
-        S[rows, pos] += coef
-        coef = coef * val[pos]
-        pos = col[pos]
-    return S
+def test_permutation_form_matches_brute_force_on_general_rows():
+    """One nonzero per row but not a permutation (two rows may point at one
+    column): the row walk still equals explicit powers."""
+    rng = np.random.default_rng(4)
+    n = 12
+    A = np.zeros((n, n))
+    A[np.arange(n), rng.integers(0, n, n)] = rng.choice([-0.5, 0.25, 0.75], n)
+    assert np.allclose(series.permutation_form(A, 7), series.brute_force(A, 7), rtol=0, atol=1e-15)
+    with pytest.raises(ValueError):
+        series.permutation_form(np.ones((3, 3)), 4)
 
 
 def test_cyclic_powers_are_single_bits():

@@ -83,7 +83,6 @@ def test_batched_exact_on_signed_cycles(ns, method):
     j <= 16, so the FP32 batched kernel is exact and must equal S_16 in every
     element, for every n the tile shapes meet (n = 1 .. 3 wrap the cycle
     around, which keeps the sums within 17 bits)."""
-    from test_dyadic_exact import sk_signed_cycle
     rng = np.random.default_rng(5)
     sizes = [1, 2, 3, 8, 13, 16, 32, 50, 64, 65, 100, 128, 129, 200, 255, 256] * 2
     rng.shuffle(sizes)
@@ -94,7 +93,7 @@ def test_batched_exact_on_signed_cycles(ns, method):
     torch.cuda.synchronize()
     got = unpack(out.cpu().numpy(), offs, ns_)
     for M, G in zip(mats, got):
-        ref = sk_signed_cycle(M, 16)
+        ref = series.permutation_form(M, 16)
         assert np.array_equal(G.astype(np.float64), ref), (method, M.shape[0])
 
 

@@ -21,7 +21,7 @@ any-k schedule's T_5(A^6) at k = 30, with A^24 beside I (k = 75 would put
 A^60 beside I in one operand).  The int8 residual is exact while a column
 of Y needs at most 7 s bits (Hensel at k = 32 needs 16).
 
-References: the oracle at n = 300; the closed form ``sk_signed_cycle``
+References: the oracle at n = 300; the closed form ``series.permutation_form``
 (pinned to exact rationals and to the oracle in ``test_dyadic_exact.py``) at
 the panel, large-tile and full (n = 8192) sizes, where the oracle's FP64
 products would take the test past a minute.
@@ -34,7 +34,6 @@ import pytest
 
 import workloads
 from oracle import series
-from test_dyadic_exact import sk_signed_cycle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -94,7 +93,7 @@ def test_small_tiles_equal_oracle(ns, method, k, k16, dtypes):
         kk = k16 if dtype == "f16_scaled" else k
         if kk not in refs:
             refs[kk], _ = series.evaluate(A, kk, method)
-            assert np.array_equal(refs[kk], sk_signed_cycle(A, kk))
+            assert np.array_equal(refs[kk], series.permutation_form(A, kk))
         say(f"[gpu] exact cyclic {method} k={kk} {dtype} n=300")
         got, _ = run(ns, A, kk, method, dtype)
         check(got, refs[kk], method, dtype, kk)
@@ -113,7 +112,7 @@ def test_large_tiles_equal_closed_form(ns, n, method, k, k16, dtypes):
     for dtype in dtypes:
         kk = k16 if dtype == "f16_scaled" else k
         if kk not in refs:
-            refs[kk] = sk_signed_cycle(A, kk)
+            refs[kk] = series.permutation_form(A, kk)
         say(f"[gpu] exact cyclic {method} k={kk} {dtype} n={n}")
         got, rep = run(ns, A, kk, method, dtype)
         check(got, refs[kk], method, dtype, kk, n)
@@ -132,7 +131,7 @@ def test_full_size_exact(ns, method, k, k16):
     for dtype in ALL:
         kk = k16 if dtype == "f16_scaled" else k
         if kk not in refs:
-            refs[kk] = sk_signed_cycle(A, kk)
+            refs[kk] = series.permutation_form(A, kk)
         say(f"[gpu] exact cyclic {method} k={kk} {dtype} n={n}")
         got, rep = run(ns, A, kk, method, dtype)
         check(got, refs[kk], method, dtype, kk, n)
@@ -148,6 +147,6 @@ def test_int8_residual_exact_cyclic(ns, n, dtype):
     A = cyc(n)
     say(f"[gpu] exact cyclic hensel k=32 {dtype} n={n}")
     got, rep = run(ns, A, 32, "hensel", dtype)
-    check(got, sk_signed_cycle(A, 32), dtype, n)
+    check(got, series.permutation_form(A, 32), dtype, n)
     # the final residual is A^32 exactly: a signed permutation times 2^-32
     assert rep["level_norm"][-1] == pytest.approx(np.sqrt(n) * 2.0 ** -32, rel=1e-15)
