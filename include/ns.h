@@ -116,12 +116,12 @@ enum ns_dtype {
    change only how the product A Y of the residual R = I - (I - A) Y of
    eq. (8) (Sec. 5.3) is computed; without one it is an FP64 MFMA product at
    every level.  Any other combination is NS_ERR_UNSUPPORTED.
-     NS_RESID_LAST: the exact (FP64, or int8-emulated with NS_RESID_INT8)
-       residual only at the last two levels -- the residual the final update
-       uses and the reported final one; the earlier ones are products of the
-       working precision, whose error the next exact residual sees and the
-       update after it removes (Lemma 5.9: R_(n+1) = E(R_n) for the true
-       residual of each iterate).
+     NS_RESID_LAST: the exact (FP64, or emulated with NS_RESID_INT8 or
+       NS_RESID_CRT) residual only at the last two levels -- the residual the
+       final update uses and the reported final one; the earlier ones are
+       products of the working precision, whose error the next exact
+       residual sees and the update after it removes (Lemma 5.9:
+       R_(n+1) = E(R_n) for the true residual of each iterate).
      NS_RESID_INT8(s): the residual product emulated from s int8 slices per
        operand (1 <= s <= 8; s = 0 means 7): X = A by rows and Y by columns are
        cut into signed 7-bit digits under a per-row / per-column power of two;
@@ -129,9 +129,19 @@ enum ns_dtype {
        with exact int32 accumulation and are summed in FP64.  Error about
        n 2^(e_i + f_j) (s + 1) 2^(-7 s), e_i and f_j the row and column
        exponents.  The padded n is a multiple of 256; s n 127^2 must stay
-       below 2^31 (NS_ERR_RANGE otherwise). */
+       below 2^31 (NS_ERR_RANGE otherwise).
+     NS_RESID_CRT: the residual product emulated through residues: A's rows
+       and Y's columns are scaled by powers of two to integers of at most 46
+       bits, reduced modulo N pairwise-coprime moduli m <= 256 (N = 13 for
+       padded n = 256, 14 from 512 to 65536) into int8, multiplied exactly
+       per modulus on int8 MFMA, and the exact integer product is rebuilt
+       with the Chinese remainder theorem in FP64 limbs.  Error about
+       n 2^(e_i + f_j - 46), the bound of NS_RESID_INT8 with s = 7, from N
+       products where that form takes 28 (Ozaki's scheme with integer moduli).
+       Excludes NS_RESID_INT8; n 2^14 must stay below 2^31. */
 #define NS_RESID_LAST 0x100
 #define NS_RESID_INT8(s) (0x200 | ((s) << 12))
+#define NS_RESID_CRT 0x400
 
 /* ---- status ----------------------------------------------------------- */
 enum ns_status {

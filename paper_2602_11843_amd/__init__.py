@@ -33,10 +33,13 @@ def RESID_INT8(slices: int = 0) -> int:
     return 0x200 | (int(slices) << 12)
 
 
+RESID_CRT = 0x400
+
+
 def dtype_code(dtype) -> int:
     """The ns_dtype value of a dtype given as an int or as a name with
     optional residual modifiers: "split_bf16+last", "split_bf16+i8" (7
-    slices), "f16_scaled+i8x5+last"."""
+    slices), "f16_scaled+i8x5+last", "split_bf16+crt" (residues)."""
     if not isinstance(dtype, str):
         return int(dtype)
     base, *mods = dtype.split("+")
@@ -50,6 +53,8 @@ def dtype_code(dtype) -> int:
             code |= RESID_INT8(0)
         elif m.startswith("i8x") and m[3:].isdigit():
             code |= RESID_INT8(int(m[3:]))
+        elif m == "crt":
+            code |= RESID_CRT
         else:
             raise ValueError(f"unknown residual modifier {m!r} in {dtype!r}")
     return code

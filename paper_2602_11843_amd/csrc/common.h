@@ -111,6 +111,25 @@ hipError_t launch_gemm_i8(const void* xs, const void* ys, int n, int slices, dou
                           const unsigned long long* rowmax, const unsigned long long* colmax,
                           const GemmParams* epi, hipStream_t s);
 
+// The same product through residues (ozaki.hip, the NS_RESID_CRT form): X
+// and Y are scaled by rows / columns to integers of at most kCrtBits bits,
+// reduced modulo crt_moduli(n) pairwise-coprime moduli m <= 256 into int8
+// planes, multiplied exactly per modulus on int8 MFMA, and the integer
+// product is rebuilt by the Chinese remainder theorem.
+constexpr int kCrtBits = 46;
+constexpr int kMaxCrtModuli = 16;
+// number of moduli for padded n (their product exceeds n 2^(2 kCrtBits + 2))
+int crt_moduli(int n);
+// residue planes (crt_moduli(n) n^2 bytes) of src by rows (transpose = 0) or
+// columns (1), exponents from mx
+hipError_t launch_crt_slices(const double* src, int n, int transpose, const unsigned long long* mx,
+                             void* dst, hipStream_t s);
+// X Y from the residue planes; tplanes (crt_moduli(n) n^2 bytes) holds each
+// modulus' reduced product until the combining launch applies epi
+hipError_t launch_gemm_crt(const void* xs, const void* ys, int n, void* tplanes,
+                           const unsigned long long* rowmax, const unsigned long long* colmax,
+                           const GemmParams* epi, hipStream_t s);
+
 // Elementwise helpers (util.hip).
 // dst (padded n_pad x n_pad, ld n_pad) <- src (n x n, lda) converted; the
 // padding is zero.  *_f64 flags give element types.

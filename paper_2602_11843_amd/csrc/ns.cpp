@@ -124,11 +124,12 @@ struct Scalars {                          // layout of the scalar block in devic
 static_assert(sizeof(Scalars) <= kScalarBytes, "scalar block too small");
 
 // A dtype argument is a base precision (low byte) plus residual-product
-// modifiers (NS_RESID_LAST, NS_RESID_INT8(s)).
+// modifiers (NS_RESID_LAST, NS_RESID_INT8(s), NS_RESID_CRT).
 constexpr int kBaseMask = 0xff, kResidInt8 = 0x200, kSliceShift = 12;
-constexpr int kModifierBits = NS_RESID_LAST | kResidInt8 | (0xf << kSliceShift);
+constexpr int kModifierBits = NS_RESID_LAST | kResidInt8 | NS_RESID_CRT | (0xf << kSliceShift);
 int base_of(int dtype) { return dtype & kBaseMask; }
 bool resid_last(int dtype) { return (dtype & NS_RESID_LAST) != 0; }
+bool resid_crt(int dtype) { return (dtype & NS_RESID_CRT) != 0; }
 // slices of the int8-emulated residual product, 0 without the modifier
 int resid_slices(int dtype) {
   if (!(dtype & kResidInt8)) return 0;
@@ -283,7 +284,7 @@ int plan(int64_t k, int method, int64_t* k_eff, int32_t* levels, int32_t* gemms)
 
 int n_internal(int64_t n, int dtype) {
   const Engine e = work_engine(dtype);
-  const int i8 = resid_slices(dtype) ? i8_tile() : 1;
+  const int i8 = (resid_slices(dtype) || resid_crt(dtype)) ? i8_tile() : 1;
   int t = std::max(engine_tile(e, (int)n), i8);
   if (is_mixed(dtype)) t = std::max(t, engine_tile(ENG_F64, (int)n));
   int np = (int)((n + t - 1) / t * t);
@@ -315,11 +316,18 @@ void buffer_counts(int method, int dtype, int* nw, int* n64) {
 }
 
 // bytes of the int8-emulated residual's buffers: digit planes of both
-// operands, the FP64 partial sums, row and column max-abs
-size_t i8_bytes(int np, int slices) {
+// operands, the FP64 partial sums, row and column max-abs.  The residue form:
+// residue planes of both operands and the reduced products, max-abs.
+size_t i8_bytes(int np, int slices, bool crt) {
   if (!slices) return 0;
   const size_t mat = (size_t)np * np;
+  if (crt) return 3 * slices * mat + 2 * 8 * (size_t)np + 4 * 256;
   return 2 * slices * mat + 8 * mat + 2 * 8 * (size_t)np + 4 * 256;
+}
+
+// planes per operand of the emulated residual: slices, or moduli
+int resid_planes(int dtype, int np) {
+  return resid_crt(dtype) ? crt_moduli(np) : resid_slices(dtype);
 }
 
 size_t workspace_bytes(int64_t n, int method, int dtype) {
@@ -329,7 +337,7 @@ size_t workspace_bytes(int64_t n, int method, int dtype) {
   const size_t w = (base_of(dtype) == NS_F64) ? 8 : 4;
   const size_t mat = (size_t)np * np;
   return kScalarBytes + mat * (nw * w + n64 * 8) + 256 * (nw + n64 + 1) +
-         i8_bytes(np, resid_slices(dtype));
+         i8_bytes(np, resid_planes(dtype, np), resid_crt(dtype));
 }
 
 // ---------------------------------------------------------------------------
@@ -370,6 +378,8 @@ struct Op {
   unsigned long long* cmax;
   double* acc;
   int slices;
+  bool crt;          // SLICES / GEMM on ENG_I8: the residue form (planes are residues)
+  void* tplanes;     // GEMM on ENG_I8, residue form: the reduced products
 };
 
 // Device memory of a call that allocates nothing (ns_eval_noalloc): the
@@ -398,6 +408,8 @@ struct Ctx {
   // int8-emulated residual products (NS_RESID_INT8): slice count, buffers, and
   // the X operand whose planes are current (A, sliced once per call)
   int slices = 0;
+  bool crt = false;          // the residue form (NS_RESID_CRT): slices counts moduli
+  void* i8_t = nullptr;      // its reduced products
   bool resid_last = false;
   void* i8_x = nullptr;
   void* i8_y = nullptr;
@@ -511,6 +523,8 @@ struct Ctx {
       op.rmax = i8_rmax;
       op.cmax = i8_cmax;
       op.slices = slices;
+      op.crt = crt;
+      op.tplanes = i8_t;
     } else if (panel_path(e, np)) {
       panels(e, X, 0, panel_x);
       panels(e, Y, 1, panel_y);
@@ -598,6 +612,7 @@ struct Ctx {
     op.rmax = mx;
     op.dst = dst;
     op.slices = slices;
+    op.crt = crt;
     ops.push_back(op);
   }
 
@@ -726,8 +741,12 @@ struct Ctx {
         continue;
       }
       if (op.kind == Op::SLICES) {
-        NS_HIP(launch_i8_slices(static_cast<const double*>(op.ptr), np, op.transpose, op.rmax,
-                                op.slices, op.dst, s));
+        if (op.crt)
+          NS_HIP(launch_crt_slices(static_cast<const double*>(op.ptr), np, op.transpose, op.rmax,
+                                   op.dst, s));
+        else
+          NS_HIP(launch_i8_slices(static_cast<const double*>(op.ptr), np, op.transpose, op.rmax,
+                                  op.slices, op.dst, s));
         continue;
       }
       // an independent next product shares this launch
@@ -750,7 +769,9 @@ struct Ctx {
         NS_HIP(hipEventRecord(e0, s));
       }
       hipError_t err;
-      if (op.e == ENG_I8)
+      if (op.e == ENG_I8 && op.crt)
+        err = launch_gemm_crt(op.p.X, op.p.Y, np, op.tplanes, op.rmax, op.cmax, pd + gi, s);
+      else if (op.e == ENG_I8)
         err = launch_gemm_i8(op.p.X, op.p.Y, np, op.slices, op.acc, op.rmax, op.cmax, pd + gi, s);
       else if (op.panels) err = launch_gemm_panels(op.e, op.p, pd + gi, s);
       else if (pair) err = launch_gemm(op.e, op.p, pd + gi, s, &ops[oi + 1].p, pd + gi + 1);
@@ -1043,10 +1064,15 @@ int check_args(const void* A, int64_t n, int64_t lda, int64_t k, int method, int
       return fail(NS_ERR_ARG, "slice count without NS_RESID_INT8 (dtype 0x%x)", dtype);
     if (resid_slices(dtype) > kMaxI8Slices)
       return fail(NS_ERR_ARG, "NS_RESID_INT8 takes 1 to %d slices", kMaxI8Slices);
+    if ((dtype & kResidInt8) && resid_crt(dtype))
+      return fail(NS_ERR_ARG, "NS_RESID_INT8 and NS_RESID_CRT exclude each other");
     if (!is_mixed(dtype) || !is_residual(method))
       return fail(NS_ERR_UNSUPPORTED,
                   "residual modifiers need a residual method in an FP64-accumulating dtype");
     const int64_t np = n_internal(n, dtype);
+    if (resid_crt(dtype) && (!crt_moduli((int)np) || np * 128 * 128 >= ((int64_t)1 << 31)))
+      return fail(NS_ERR_RANGE, "NS_RESID_CRT at padded n = %lld: beyond its moduli or int32 sums",
+                  (long long)np);
     if ((int64_t)resid_slices(dtype) * np * 127 * 127 >= ((int64_t)1 << 31))
       return fail(NS_ERR_RANGE, "%d int8 slices at padded n = %lld overflow int32 accumulation",
                   resid_slices(dtype), (long long)np);
@@ -1119,19 +1145,25 @@ int eval_core(ns_handle* h, const FixedMem* fx, const void* A, int64_t n, int64_
   c.eng = work_engine(dtype);
   c.mixed = is_mixed(dtype);
   c.resid_last = resid_last(dtype);
-  c.slices = resid_slices(dtype);
+  c.crt = resid_crt(dtype);
+  c.slices = resid_planes(dtype, c.np);
   c.scal = reinterpret_cast<Scalars*>(ws);
   c.arena = ws + kScalarBytes;
   c.zero(c.scal, sizeof(Scalars));
   if (c.slices) {
     // the int8-emulated residual's buffers sit at the end of the workspace
     const size_t mat = (size_t)c.np * c.np;
-    char* q = ws + need - i8_bytes(c.np, c.slices);
+    char* q = ws + need - i8_bytes(c.np, c.slices, c.crt);
     q = reinterpret_cast<char*>(((uintptr_t)q + 255) & ~(uintptr_t)255);
     c.i8_x = q;
     c.i8_y = q + c.slices * mat;
-    c.i8_acc = reinterpret_cast<double*>(q + 2 * c.slices * mat);
-    c.i8_rmax = reinterpret_cast<unsigned long long*>(q + 2 * c.slices * mat + 8 * mat);
+    if (c.crt) {
+      c.i8_t = q + 2 * c.slices * mat;
+      c.i8_rmax = reinterpret_cast<unsigned long long*>(q + 3 * c.slices * mat);
+    } else {
+      c.i8_acc = reinterpret_cast<double*>(q + 2 * c.slices * mat);
+      c.i8_rmax = reinterpret_cast<unsigned long long*>(q + 2 * c.slices * mat + 8 * mat);
+    }
     c.i8_cmax = c.i8_rmax + c.np;
   }
 

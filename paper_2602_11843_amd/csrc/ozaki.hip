@@ -32,6 +32,19 @@
 // the last diagonal adds the FP64 partial sum of the earlier ones, scales by
 // 2^(e_i + f_j) and applies the product's affine epilogue; the others write
 // their partial sum (FP64) to an accumulator matrix.
+//
+// Residue form (NS_RESID_CRT).  X_ij = 2^e_i x with |x| < 1 becomes the integer
+// X'_ij = rint(2^B x), |X'| <= 2^B (B = kCrtBits), and Y'_ij likewise by
+// columns, so X Y ~ 2^(e_i + f_j - 2B) X'Y' with an error of about
+// n 2^(e_i + f_j - B), the int8 form's bound at s = 7.  X'Y' is an exact
+// integer with |X'Y'| <= n 2^2B.  For pairwise-coprime moduli m_1..m_N <= 256
+// with product M > 4 n 2^2B, the residues of X' and Y' modulo m_l fit int8
+// (symmetric range), one int8 product per modulus gives X'Y' mod m_l exactly
+// (int32 sums of n products of at most 2^14), and the Chinese remainder
+// theorem rebuilds X'Y' = sum_l M_l t_l - q M (M_l = M / m_l, t_l = (X'Y' mod
+// m_l) (M_l^-1 mod m_l) mod m_l, q the nearest integer to that sum over M)
+// with FP64 limbs of 32 bits, every step exact until the final conversion.
+// N = 14 products at n = 8192 where the int8 form at s = 7 takes 28.
 #include "ydirect.h"
 
 namespace ns {
@@ -87,9 +100,29 @@ __global__ __launch_bounds__(256) void maxabs_rc_kernel(const double* __restrict
 // 1: M = src^T, i.e. by columns), with the exponent of M's row r from mx[r].
 // One workgroup per 64 x 64 region of M, staged in LDS as M[r][k]; each thread
 // then writes one 16-byte chunk of every plane.
+// Moduli of the residue form, as the slicing kernel takes them.
+struct CrtMods {
+  int n;
+  double m[kMaxCrtModuli];
+  double inv[kMaxCrtModuli];    // 1 / m, rounded
+};
+
+// int8 residue of the integer x (|x| < 2^53) modulo m, in the symmetric range
+// (r - m for r > 127: at least -128 for m = 256, -127 for odd m)
+__device__ __forceinline__ unsigned residue8(double x, double m, double inv) {
+  const double q = floor(x * inv);
+  double r = fma(-q, m, x);                   // exact: |q m| < 2^54 and r is an integer
+  if (r < 0.0) r += m;
+  else if (r >= m) r -= m;
+  int ri = (int)r;
+  if (ri > 127) ri -= (int)m;
+  return (unsigned)ri & 0xffu;
+}
+
+template <bool CRT>
 __global__ __launch_bounds__(256) void slices_kernel(const double* __restrict__ src, int n,
                                                      int transpose, const u64* __restrict__ mx,
-                                                     int s, int8_t* __restrict__ dst) {
+                                                     int s, int8_t* __restrict__ dst, CrtMods cm) {
   __shared__ double t[64][65];
   const int r0 = 64 * blockIdx.y, k0 = 64 * blockIdx.x, tid = threadIdx.x;
 #pragma unroll
@@ -130,6 +163,22 @@ __global__ __launch_bounds__(256) void slices_kernel(const double* __restrict__ 
     x[i] = (v == v && fabs(v) < 1.0) ? v : 0.0;   // non-finite rows are flagged by the product
   }
   const size_t plane = (size_t)n * n;
+  if constexpr (CRT) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = rint(ldexp(x[i], kCrtBits));   // |x| <= 2^B, an integer
+    for (int p = 0; p < cm.n; ++p) {
+      i32x4 w;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        unsigned b = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b |= residue8(x[4 * q + i], cm.m[p], cm.inv[p]) << (8 * i);
+        w[q] = (int)b;
+      }
+      *reinterpret_cast<i32x4*>(dst + p * plane + off) = w;
+    }
+    return;
+  }
   for (int p = 0; p < s; ++p) {
     i32x4 w;
 #pragma unroll
@@ -159,6 +208,10 @@ struct I8Args {
   const u64* rowmax;        // X row max-abs bits
   const u64* colmax;        // Y column max-abs bits
   const GemmParams* epi;    // the product's epilogue (device), read by the last launch
+  // residue form: with tout set, the launch writes t = (P mod m) y mod m of its
+  // int32 product P as bytes to tout (row-major n x n) and nothing else
+  int crt_m = 0, crt_y = 0;
+  uint8_t* tout = nullptr;
 };
 
 // 128 x 256 tile, 4 waves of 128 x 64 (4 x 2 fragments of
@@ -247,6 +300,17 @@ __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_i8_kernel(const I8Ar
       const int r = v / VPR, cv = (v % VPR) * VEC;
       const int row = grow + r, col = col0 + cv;
       const size_t idx = (size_t)row * n + col;
+      if (args.tout) {
+        unsigned w = 0;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          int rm = C[r * Q::CPITCH + cv + e] % args.crt_m;
+          if (rm < 0) rm += args.crt_m;
+          w |= (unsigned)((rm * args.crt_y) % args.crt_m) << (8 * e);
+        }
+        *reinterpret_cast<unsigned*>(args.tout + idx) = w;
+        continue;
+      }
       double c[VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) c[e] = (double)C[r * Q::CPITCH + cv + e] * dscale;
@@ -274,6 +338,86 @@ __global__ __launch_bounds__(Q::THREADS, Q::MINB) void gemm_i8_kernel(const I8Ar
   if (args.last) publish_stats<Q::THREADS>(*p, st, reinterpret_cast<double*>(smem));
 }
 
+// Chinese-remainder constants of one padded n.
+struct CrtConsts {
+  int n;                          // moduli
+  double ml[kMaxCrtModuli][4];    // M / m_l in 32-bit limbs, low first
+  double mm[4];                   // M in 32-bit limbs
+  double md;                      // M, rounded
+};
+
+// Rebuild X'Y' from its reduced residues t_l, scale by 2^(e_i + f_j - 2B) and
+// apply the product's epilogue: four consecutive elements of one row per
+// thread, 1024 columns per workgroup.
+__global__ __launch_bounds__(256) void crt_combine_kernel(const uint8_t* __restrict__ t, int n,
+                                                          CrtConsts cc, const u64* __restrict__ rowmax,
+                                                          const u64* __restrict__ colmax,
+                                                          const GemmParams* __restrict__ epi) {
+  __shared__ double scratch[(3 + kMaxOut) * 4];
+  const int bpr = (n + 1023) / 1024;
+  const int row = blockIdx.x / bpr, col = (blockIdx.x % bpr) * 1024 + 4 * threadIdx.x;
+  constexpr double TWO32 = 4294967296.0, INV32 = 1.0 / 4294967296.0;
+  EpiState st{0.0, 0.f, 0};
+  if (col < n) {
+    const size_t idx = (size_t)row * n + col;
+    const size_t plane = (size_t)n * n;
+    double L[4][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) L[e][j] = 0.0;
+    for (int l = 0; l < cc.n; ++l) {
+      const unsigned w = *reinterpret_cast<const unsigned*>(t + l * plane + idx);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double te = (double)((w >> (8 * e)) & 0xffu);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) L[e][j] = fma(te, cc.ml[l][j], L[e][j]);   // < 2^44: exact
+      }
+    }
+    const u64 rb = rowmax[row];
+    const int er = exp_above(rb);
+    double c[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double* v = L[e];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {            // limbs into [0, 2^32)
+        const double cr = floor(v[j] * INV32);
+        v[j] = fma(-cr, TWO32, v[j]);
+        v[j + 1] += cr;
+      }
+      const double sd = ((v[3] * TWO32 + v[2]) * TWO32 + v[1]) * TWO32 + v[0];
+      const double q = rint(sd / cc.md);       // the sum is within M / 4 of q M
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = fma(-q, cc.mm[j], v[j]);
+      double sg = 1.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double cr = floor(v[j] * INV32);
+        v[j] = fma(-cr, TWO32, v[j]);
+        v[j + 1] += cr;
+      }
+      if (v[3] < 0.0) {                        // negative: take the magnitude's limbs
+        sg = -1.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = -v[j];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double cr = floor(v[j] * INV32);
+          v[j] = fma(-cr, TWO32, v[j]);
+          v[j + 1] += cr;
+        }
+      }
+      const double z = sg * (((v[3] * TWO32 + v[2]) * TWO32 + v[1]) * TWO32 + v[0]);
+      const u64 cb = colmax[col + e];
+      c[e] = (max_finite(rb) && max_finite(cb)) ? ldexp(z, er + exp_above(cb) - 2 * kCrtBits) : NAN;
+    }
+    epi_vec<4>(*epi, row, col, c, st);
+  }
+  publish_stats<256>(*epi, st, scratch);
+}
+
 }  // namespace
 }  // namespace dev
 
@@ -290,8 +434,8 @@ hipError_t launch_maxabs_rc(const double* src, int n, unsigned long long* rowmax
 hipError_t launch_i8_slices(const double* src, int n, int transpose, const unsigned long long* mx,
                             int slices, void* dst, hipStream_t s) {
   if (n % 64 || slices < 1 || slices > kMaxI8Slices) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dev::slices_kernel, dim3(n / 64, n / 64), dim3(256), 0, s, src, n, transpose,
-                     mx, slices, static_cast<int8_t*>(dst));
+  hipLaunchKernelGGL(dev::slices_kernel<false>, dim3(n / 64, n / 64), dim3(256), 0, s, src, n, transpose,
+                     mx, slices, static_cast<int8_t*>(dst), dev::CrtMods{});
   return hipGetLastError();
 }
 
@@ -310,6 +454,94 @@ hipError_t launch_gemm_i8(const void* xs, const void* ys, int n, int slices, dou
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+namespace {
+
+// Pairwise-coprime moduli, largest first (256 = 2^8; 255 = 3 5 17;
+// 253 = 11 23; 247 = 13 19; 217 = 7 31; the others prime).
+constexpr int kCrtModuli[kMaxCrtModuli] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                           229, 227, 223, 217, 211, 199, 197, 193};
+typedef unsigned __int128 u128;
+
+// (a^-1) mod m for gcd(a, m) = 1
+int inverse_mod(int a, int m) {
+  int r0 = m, r1 = a % m, s0 = 0, s1 = 1;
+  while (r1) {
+    const int q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+    r0 = r1; r1 = r2; s0 = s1; s1 = s2;
+  }
+  return ((s0 % m) + m) % m;
+}
+
+void limbs(u128 v, double (&out)[4]) {
+  for (int j = 0; j < 4; ++j) {
+    out[j] = (double)(unsigned long long)(v & 0xffffffffu);
+    v >>= 32;
+  }
+}
+
+}  // namespace
+
+int crt_moduli(int n) {
+  const u128 need = (u128)n << (2 * kCrtBits + 2);
+  u128 M = 1;
+  for (int l = 0; l < kMaxCrtModuli; ++l) {
+    M *= (u128)kCrtModuli[l];
+    if (M > need) return l + 1;
+  }
+  return 0;   // n too large for the table
+}
+
+hipError_t launch_crt_slices(const double* src, int n, int transpose, const unsigned long long* mx,
+                             void* dst, hipStream_t s) {
+  const int N = crt_moduli(n);
+  if (n % 64 || N == 0) return hipErrorInvalidValue;
+  dev::CrtMods cm{};
+  cm.n = N;
+  for (int l = 0; l < N; ++l) {
+    cm.m[l] = kCrtModuli[l];
+    cm.inv[l] = 1.0 / kCrtModuli[l];
+  }
+  hipLaunchKernelGGL(dev::slices_kernel<true>, dim3(n / 64, n / 64), dim3(256), 0, s, src, n, transpose,
+                     mx, N, static_cast<int8_t*>(dst), cm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_crt(const void* xs, const void* ys, int n, void* tplanes,
+                           const unsigned long long* rowmax, const unsigned long long* colmax,
+                           const GemmParams* epi, hipStream_t s) {
+  using Q = dev::PolI8;
+  const int N = crt_moduli(n);
+  if (n % Q::BM || n % Q::BN || N == 0) return hipErrorInvalidValue;
+  if ((n / 64) % Q::D) return hipErrorInvalidValue;
+  if ((long long)n * 128 * 128 >= (1LL << 31)) return hipErrorInvalidValue;   // int32 sums
+  u128 M = 1;
+  for (int l = 0; l < N; ++l) M *= (u128)kCrtModuli[l];
+  dev::CrtConsts cc{};
+  cc.n = N;
+  limbs(M, cc.mm);
+  cc.md = (double)M;
+  const size_t plane = (size_t)n * n;   // bytes of one residue plane
+  const int grid = (n / Q::BM) * (n / Q::BN);
+  for (int l = 0; l < N; ++l) {
+    const int m = kCrtModuli[l];
+    const u128 Ml = M / (u128)m;
+    limbs(Ml, cc.ml[l]);
+    dev::I8Args a{static_cast<const uint16_t*>(xs) + l * plane / 2,
+                  static_cast<const uint16_t*>(ys) + l * plane / 2, n, 2, 1, 0, nullptr, rowmax,
+                  colmax, nullptr};
+    a.crt_m = m;
+    a.crt_y = inverse_mod((int)(Ml % (u128)m), m);
+    a.tout = static_cast<uint8_t*>(tplanes) + l * plane;
+    hipLaunchKernelGGL(dev::gemm_i8_kernel<Q>, dim3(grid), dim3(Q::THREADS), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int bpr = (n + 1023) / 1024;
+  hipLaunchKernelGGL(dev::crt_combine_kernel, dim3(n * bpr), dim3(256), 0, s,
+                     static_cast<const uint8_t*>(tplanes), n, cc, rowmax, colmax, epi);
+  return hipGetLastError();
 }
 
 }  // namespace ns

@@ -140,10 +140,12 @@ def test_full_size_exact(ns, method, k, k16):
 
 
 @pytest.mark.parametrize("n", [300, 3072, 8192])
-@pytest.mark.parametrize("dtype", ["f32_acc64+i8", "split_bf16+i8+last", "f16_scaled+i8x6"])
+@pytest.mark.parametrize("dtype", ["f32_acc64+i8", "split_bf16+i8+last", "f16_scaled+i8x6",
+                                   "split_bf16+crt", "f16_scaled+crt+last"])
 def test_int8_residual_exact_cyclic(ns, n, dtype):
-    """Hensel at k = 32 with the int8-emulated residual: A's rows need one
-    digit and Y's columns (S_16) three, within the s + 1 digit-pair bound."""
+    """Hensel at k = 32 with the emulated residual: A's rows need one digit
+    and Y's columns (S_16) three, within the s + 1 digit-pair bound; in the
+    residue form both fit 46-bit integers exactly."""
     A = cyc(n)
     say(f"[gpu] exact cyclic hensel k=32 {dtype} n={n}")
     got, rep = run(ns, A, 32, "hensel", dtype)

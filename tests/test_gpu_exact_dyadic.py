@@ -79,7 +79,7 @@ def test_every_engine_exact(ns, n, method):
 
 @pytest.mark.parametrize("n", [300, 3072])
 @pytest.mark.parametrize("dtype", ["f32_acc64+i8", "split_bf16+i8", "f16_scaled+i8+last",
-                                   "split_bf16+i8x6"])
+                                   "split_bf16+i8x6", "split_bf16+crt", "f32_acc64+crt+last"])
 def test_int8_residual_exact(ns, n, dtype):
     """Hensel's residual product through the int8 slices: the digits of A's
     rows and Y's columns hold their values exactly, so the emulated FP64

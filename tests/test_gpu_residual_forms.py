@@ -1,5 +1,5 @@
-"""GPU parity of the residual-product variants (NS_RESID_LAST, NS_RESID_INT8)
-of the FP64-accumulating residual forms (Sec. 5.3, eq. (8)).
+"""GPU parity of the residual-product variants (NS_RESID_LAST, NS_RESID_INT8,
+NS_RESID_CRT) of the FP64-accumulating residual forms (Sec. 5.3, eq. (8)).
 
 Reference: the oracle's FP64 schedule of the same method on the same input.
 Bars: every variant within its base dtype's bar (split-BF16 1e-4, FP32 1e-5,
@@ -8,6 +8,8 @@ scaled FP16 1e-2), and the accuracy class the variant exists for:
   - int8 slices with s = 7 carry about 2^-49 n relative error in A Y, like
     an FP64 product: the result is within 2x of the FP64-residual form's;
   - s = 6 stays within 1e-9 on these inputs, s = 4 within 1e-5;
+  - the residue form has the s = 7 bound (46-bit integers rebuilt exactly):
+    within 2x of the FP64-residual form's too;
   - NS_RESID_LAST: the residual the final update uses is exact, so for the
     FP32 and split-BF16 forms the result is within 2x of the FP64-residual
     form's (the scaled-FP16 form loses more: its first residual's error
@@ -78,17 +80,19 @@ def case_1000():
 def test_residual_variants_radix9(ns, handle, case_1000, base):
     w, ref = case_1000
     err = {}
-    for mod in ("", "+last", "+i8", "+i8x6", "+i8x4", "+i8+last"):
+    for mod in ("", "+last", "+i8", "+i8x6", "+i8x4", "+i8+last", "+crt", "+crt+last"):
         got, rep, eng = run(ns, handle, w.A, 729, "radix9_resid", base + mod, timing=True)
         assert rep["gemms_performed"] == 15 and not rep["nonfinite"]
         err[mod] = assert_close(got, ref, BAR[base], f"{base}{mod}")[0]
         # which engine computed the three residual products
         wp = {"split_bf16": "split_bf16", "f32_acc64": "f32", "f16_scaled": "f16_scaled"}[base]
-        exact = eng[ns.RESID_INT8(0)] if "i8" in mod else eng["f64"]
+        exact = eng[ns.RESID_INT8(0)] if ("i8" in mod or "crt" in mod) else eng["f64"]
         assert exact == (2 if "last" in mod else 3), (mod, eng)
         assert eng[wp] == 12 + (1 if "last" in mod else 0), (mod, eng)
     assert err["+i8"] <= 2 * err[""] + 1e-13
     assert err["+i8+last"] <= 2 * err["+last"] + 1e-13
+    assert err["+crt"] <= 2 * err[""] + 1e-13
+    assert err["+crt+last"] <= 2 * err["+last"] + 1e-13
     assert err["+i8x6"] <= max(1e-9, 2 * err[""])
     assert err["+i8x4"] <= 1e-5
     if base != "f16_scaled":
@@ -105,10 +109,13 @@ def test_int8_residual_tiles_and_tails(ns, handle, n):
     ref = series.radix15c(w.A, k)[0]
     f64, _, _ = run(ns, handle, w.A, k, "radix15c", "split_bf16")
     i8, rep, _ = run(ns, handle, w.A, k, "radix15c", "split_bf16+i8")
-    assert rep["n_internal"] % 256 == 0
+    crt, rep2, _ = run(ns, handle, w.A, k, "radix15c", "split_bf16+crt")
+    assert rep["n_internal"] % 256 == 0 and rep2["n_internal"] == rep["n_internal"]
     e64 = assert_close(f64, ref, BAR["split_bf16"], "fp64 residual")[0]
     e8 = assert_close(i8, ref, BAR["split_bf16"], "int8 residual")[0]
+    ec = assert_close(crt, ref, BAR["split_bf16"], "residue-form residual")[0]
     assert e8 <= 2 * e64 + 1e-13
+    assert ec <= 2 * e64 + 1e-13
 
 
 def test_int8_residual_hensel_nonsymmetric(ns, handle):
@@ -116,9 +123,10 @@ def test_int8_residual_hensel_nonsymmetric(ns, handle):
     input, FP32 products with the int8 residual, against the oracle."""
     g = workloads.gaussian(300, 0.8, 17)
     ref = series.hensel(g.A, 64)[0]
-    got, rep, _ = run(ns, handle, g.A, 64, "hensel", "f32_acc64+i8")
-    assert_close(got, ref, BAR["f32_acc64"], "hensel f32_acc64+i8")
-    assert not rep["nonfinite"]
+    for dt in ("f32_acc64+i8", "f32_acc64+crt"):
+        got, rep, _ = run(ns, handle, g.A, 64, "hensel", dt)
+        assert_close(got, ref, BAR["f32_acc64"], f"hensel {dt}")
+        assert not rep["nonfinite"]
 
 
 def test_residual_modifier_errors(ns, handle):
@@ -128,7 +136,9 @@ def test_residual_modifier_errors(ns, handle):
     A = torch.eye(64, dtype=torch.float64, device="cuda") * 0.5
     bad = [("radix9", "split_bf16+last", -2), ("radix9_resid", "f64+i8", -2),
            ("binary", "f16_scaled+i8", -2), ("radix9_resid", ns.SPLIT_BF16 | ns.RESID_INT8(9), -1),
-           ("radix9_resid", ns.SPLIT_BF16 | (3 << 12), -1), ("radix9_resid", ns.SPLIT_BF16 | 0x400, -1)]
+           ("radix9_resid", ns.SPLIT_BF16 | (3 << 12), -1), ("radix9_resid", ns.SPLIT_BF16 | 0x800, -1),
+           ("radix9", "split_bf16+crt", -2), ("radix9_resid", "f64+crt", -2),
+           ("radix9_resid", ns.SPLIT_BF16 | ns.RESID_INT8(0) | ns.RESID_CRT, -1)]
     for method, dtype, status in bad:
         with pytest.raises(ns.NSError) as ei:
             ns.ns_eval_ex(A, 81, method, dtype, handle=handle)
