@@ -18,7 +18,8 @@ the legs of the other workloads:
   precision_sym   radix-9 in FP32, FP32 + FP64 sum, split-BF16, scaled FP16;
                   the residual forms (FP64 residual) in split-BF16, scaled
                   FP16 and FP32; split-BF16 with the residual exact only at
-                  the last two levels, or emulated from int8 slices
+                  the last two levels, or emulated from int8 slices or
+                  through residues modulo 14 pairwise-coprime moduli
   gaussian_rho    n = 8192 FP32, nonsymmetric, rho_hat = 0.99, k = 3375:
                   radix-15 (contraction-aware table and App. B table),
                   radix-9 (k_eff 6561), binary (k_eff 4096), the exact any-k
@@ -52,19 +53,37 @@ METRIC = "S_k(A) time + GEMM TFLOP/s (%MFMA peak), radix-9/15 vs squaring at sta
 # dense MI355X peaks (TFLOP/s; int8: TOP/s)
 PEAK = {"f64": 78.6, "f32": 157.3, "split_bf16": 2516.6, "f16_scaled": 2516.6, "i8": 5000.0}
 # MFMA work per logical product on each engine (split-BF16: three BF16 products;
-# the int8-emulated residual: s (s + 1) / 2 int8 products, set per leg)
+# the int8-emulated residual: its int8 products, set per leg by i8_products)
 MFMA_PER_LOGICAL = {"f64": 1.0, "f32": 1.0, "split_bf16": 3.0, "f16_scaled": 1.0}
 ENGINES = ("f64", "f32", "split_bf16", "f16_scaled", "i8")
 
 
-def resid_slices(dtype):
-    """int8 slices of a dtype name's residual modifier (0 without one)."""
+def crt_moduli(n):
+    """Moduli of the residue form at padded n (ns.h: their product exceeds
+    n 2^94): 13 at n = 256, 14 from 512 to 65536."""
+    M, count = 1, 0
+    for m in (256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197, 193):
+        M *= m
+        count += 1
+        if M > n << 94:
+            return count
+    raise ValueError(f"n = {n} beyond the residue form's moduli")
+
+
+def i8_products(dtype, n):
+    """int8 products per emulated residual product of a dtype name: s (s + 1) / 2
+    for int8 slices (s = 7 for "+i8"), one per modulus for "+crt"; 0 without."""
     for m in dtype.split("+")[1:]:
         if m == "i8":
-            return 7
+            return 28
         if m.startswith("i8x"):
-            return int(m[3:])
+            s = int(m[3:])
+            return s * (s + 1) // 2
+        if m == "crt":
+            return crt_moduli(n)
     return 0
+
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -109,20 +128,20 @@ def kernel_name(engine, n):
         return ("gemm_panel_kernel<PolPanel<2,4,4,2,true,1,2,2>>" if n >= 3072
                 else "gemm_lowp_kernel<PolLow<2,2,1,1,true>>")
     if engine == "i8":
-        return "gemm_i8_kernel<PolI8> (one launch per slice diagonal)"
+        return "gemm_i8_kernel<PolI8> (one launch per slice diagonal, or per modulus)"
     return ("gemm_panel_kernel<PolPanel<1,4,4,2,false,...,Y in registers>>" if n >= 1792
             else "gemm_lowp_kernel<PolLow<2,2,1,1,false>>")
 
 
-def engine_roofline(engine, stats, n, slices=0):
+def engine_roofline(engine, stats, n, i8_per_product=0):
     """Roofline of one engine's product launches: MFMA work per launch (2 n^3
-    per logical product, times 3 for split-BF16, times s (s + 1) / 2 int8
-    products for the emulated residual) over the launches' average duration,
+    per logical product, times 3 for split-BF16, times the int8 products of
+    one emulated residual product) over the launches' average duration,
     against that engine's dense MFMA peak."""
     cnt, ms, flops = stats
     if not cnt or ms <= 0:
         return None
-    mfma = slices * (slices + 1) / 2 if engine == "i8" else MFMA_PER_LOGICAL[engine]
+    mfma = i8_per_product if engine == "i8" else MFMA_PER_LOGICAL[engine]
     achieved = mfma * flops / (ms * 1e-3) / 1e12
     peak = PEAK[engine]
     return {"bound": "mfma", "kernel": kernel_name(engine, n), "achieved": round(achieved, 3),
@@ -201,7 +220,7 @@ def time_leg(ns, h, A, k, method, dtype, out, steps, warmup, stream, n, separate
     h.ns_set_product_timing(False)
     _, rep = ns.ns_eval_ex(A, k, method, dtype, out=out, handle=h, stream=stream, report=True)
     flops = products * 2.0 * n ** 3
-    rooflines = {e: engine_roofline(e, st, rep["n_internal"], resid_slices(dtype))
+    rooflines = {e: engine_roofline(e, st, rep["n_internal"], i8_products(dtype, rep["n_internal"]))
                  for e, st in per_engine.items() if st[0]}
     dominant = max(rooflines, key=lambda e: per_engine[e][1]) if rooflines else None
     # per-level split of the last timed call (its launches are the last ones recorded)
@@ -334,9 +353,10 @@ def bench_precision_sym(args, torch, ns):
                    ("radix9_resid", "split_bf16"), ("radix9_resid", "f16_scaled"),
                    ("radix9_resid", "f32_acc64"),
                    # the residual product exact only at the last two levels, or
-                   # emulated from int8 slices (s = 7, 6)
+                   # emulated from int8 slices (s = 7, 6) or through residues
                    ("radix9_resid", "split_bf16+last"), ("radix9_resid", "split_bf16+i8"),
-                   ("radix9_resid", "split_bf16+i8x6"), ("radix9_resid", "split_bf16+i8+last")],
+                   ("radix9_resid", "split_bf16+i8x6"), ("radix9_resid", "split_bf16+i8+last"),
+                   ("radix9_resid", "split_bf16+crt"), ("radix9_resid", "split_bf16+crt+last")],
                   args)
     res = {}
     for method, dtype in legs:

@@ -49,6 +49,16 @@ def test_kernel_names_follow_the_tile_thresholds():
     assert "PolPanel" in bench.kernel_name("f16_scaled", 2048)
 
 
+def test_int8_products_per_residual():
+    """The roofline of the emulated residual counts s (s + 1) / 2 int8
+    products for the digit form and one per modulus for the residue form."""
+    assert bench.i8_products("split_bf16+i8", 8192) == 28
+    assert bench.i8_products("split_bf16+i8x6+last", 8192) == 21
+    assert bench.i8_products("split_bf16+crt+last", 8192) == 14
+    assert bench.i8_products("split_bf16+crt", 256) == 13
+    assert bench.i8_products("split_bf16+last", 8192) == 0
+
+
 def _fake_root(tmp_path, traffic=123456789):
     csrc = tmp_path / "paper_2602_11843_amd" / "csrc"
     csrc.mkdir(parents=True)
