@@ -343,7 +343,7 @@ struct CrtConsts {
   int n;                          // moduli
   double ml[kMaxCrtModuli][4];    // M / m_l in 32-bit limbs, low first
   double mm[4];                   // M in 32-bit limbs
-  double md;                      // M, rounded
+  double inv_md;                  // 1 / M, rounded
 };
 
 // Rebuild X'Y' from its reduced residues t_l, scale by 2^(e_i + f_j - 2B) and
@@ -361,21 +361,31 @@ __global__ __launch_bounds__(256) void crt_combine_kernel(const uint8_t* __restr
   if (col < n) {
     const size_t idx = (size_t)row * n + col;
     const size_t plane = (size_t)n * n;
+    // every plane's word is loaded before the first is used, so the loads
+    // overlap instead of each waiting for the previous one
+    unsigned w[kMaxCrtModuli];
+#pragma unroll
+    for (int l = 0; l < kMaxCrtModuli; ++l)
+      w[l] = l < cc.n ? *reinterpret_cast<const unsigned*>(t + l * plane + idx) : 0u;
+    const u64 rb = rowmax[row];
+    u64 cb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cb[e] = colmax[col + e];
     double L[4][4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int j = 0; j < 4; ++j) L[e][j] = 0.0;
-    for (int l = 0; l < cc.n; ++l) {
-      const unsigned w = *reinterpret_cast<const unsigned*>(t + l * plane + idx);
+#pragma unroll
+    for (int l = 0; l < kMaxCrtModuli; ++l) {
+      if (l >= cc.n) break;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const double te = (double)((w >> (8 * e)) & 0xffu);
+        const double te = (double)((w[l] >> (8 * e)) & 0xffu);
 #pragma unroll
         for (int j = 0; j < 4; ++j) L[e][j] = fma(te, cc.ml[l][j], L[e][j]);   // < 2^44: exact
       }
     }
-    const u64 rb = rowmax[row];
     const int er = exp_above(rb);
     double c[4];
 #pragma unroll
@@ -388,7 +398,7 @@ __global__ __launch_bounds__(256) void crt_combine_kernel(const uint8_t* __restr
         v[j + 1] += cr;
       }
       const double sd = ((v[3] * TWO32 + v[2]) * TWO32 + v[1]) * TWO32 + v[0];
-      const double q = rint(sd / cc.md);       // the sum is within M / 4 of q M
+      const double q = rint(sd * cc.inv_md);   // the sum is within M / 4 of q M
 #pragma unroll
       for (int j = 0; j < 4; ++j) v[j] = fma(-q, cc.mm[j], v[j]);
       double sg = 1.0;
@@ -410,8 +420,8 @@ __global__ __launch_bounds__(256) void crt_combine_kernel(const uint8_t* __restr
         }
       }
       const double z = sg * (((v[3] * TWO32 + v[2]) * TWO32 + v[1]) * TWO32 + v[0]);
-      const u64 cb = colmax[col + e];
-      c[e] = (max_finite(rb) && max_finite(cb)) ? ldexp(z, er + exp_above(cb) - 2 * kCrtBits) : NAN;
+      c[e] = (max_finite(rb) && max_finite(cb[e])) ? ldexp(z, er + exp_above(cb[e]) - 2 * kCrtBits)
+                                                   : NAN;
     }
     epi_vec<4>(*epi, row, col, c, st);
   }
@@ -521,7 +531,7 @@ hipError_t launch_gemm_crt(const void* xs, const void* ys, int n, void* tplanes,
   dev::CrtConsts cc{};
   cc.n = N;
   limbs(M, cc.mm);
-  cc.md = (double)M;
+  cc.inv_md = 1.0 / (double)M;
   const size_t plane = (size_t)n * n;   // bytes of one residue plane
   const int grid = (n / Q::BM) * (n / Q::BN);
   for (int l = 0; l < N; ++l) {

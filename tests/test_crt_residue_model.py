@@ -88,7 +88,7 @@ def emulate(X, Y):
             L[j] = L[j] + t.astype(np.float64) * ml[j]
     L = normalise(L)
     sd = ((L[3] * TWO32 + L[2]) * TWO32 + L[1]) * TWO32 + L[0]
-    q = np.rint(sd / float(M))
+    q = np.rint(sd * (1.0 / float(M)))
     V = normalise([L[j] - q * mm[j] for j in range(4)])
     neg = V[3] < 0
     W = normalise([np.where(neg, -V[j], V[j]) for j in range(4)])
