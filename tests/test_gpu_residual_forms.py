@@ -148,3 +148,18 @@ def test_residual_modifier_errors(ns, handle):
     torch.cuda.synchronize()
     lam = 0.5
     np.testing.assert_allclose(out.diag().cpu().numpy(), (1 - lam ** 81) / (1 - lam), rtol=1e-12)
+
+
+@pytest.mark.parametrize("mod", ["+i8", "+crt"])
+def test_emulated_residual_edge_inputs(ns, handle, mod):
+    """A = 0 gives S = I exactly (every row and column maximum is zero, so
+    every digit or residue is zero); a NaN in A is reported through the
+    nonfinite flag (its row's maximum is not finite, so the emulated
+    product writes NaN there), not raised."""
+    n = 200
+    got, rep, _ = run(ns, handle, np.zeros((n, n)), 81, "radix9_resid", "split_bf16" + mod)
+    assert np.array_equal(got, np.eye(n)) and not rep["nonfinite"]
+    A = workloads.symmetric(n, 0.7, 9).A.copy()
+    A[7, 11] = np.nan
+    _, rep, _ = run(ns, handle, A, 81, "radix9_resid", "split_bf16" + mod)
+    assert rep["nonfinite"]
