@@ -302,8 +302,9 @@ int ns_product_timing(ns_handle* h, int32_t* count, double* total_ms, double* to
    the dtype that uses it: NS_F64 (FP64 products, including the FP64 residual
    products of the mixed forms), NS_F32 (FP32 products, including those of
    NS_F32_ACC64), NS_SPLIT_BF16, NS_F16_SCALED, or NS_RESID_INT8(0) for the
-   int8-emulated residual products (one timed record per product, covering
-   all its diagonal launches).  Resets nothing. */
+   int8-emulated residual products of either form (one timed record per
+   product, covering all its diagonal launches, or all its per-modulus
+   launches and the combining pass).  Resets nothing. */
 int ns_product_timing_dtype(ns_handle* h, int dtype, int32_t* count, double* total_ms,
                             double* total_flops);
 

@@ -13,8 +13,8 @@
 // diagonal d = p + q share their scale, so one diagonal is ONE int8 product
 // over the k-concatenation of its d - 1 slice pairs; the longest (d = s + 1)
 // sums s n products of two digits, exact while s n 127^2 < 2^31 (n up to
-// 16384 for s = 8).  The dropped pairs and
-// the digit remainders bound the error by about n 2^(e_i + f_j) (s + 1) 2^-7s.
+// 16384 for s = 8).  The dropped pairs and the digit remainders bound the
+// error by about n 2^(e_i + f_j) (s + 1) 2^-7s.
 //
 // Layout.  The digits of plane p (p = 0..s-1) form a panel of the n x n int8
 // matrix M (X by rows; Y^T, i.e. Y by columns).  X's planes have the byte
@@ -96,10 +96,6 @@ __global__ __launch_bounds__(256) void maxabs_rc_kernel(const double* __restrict
   }
 }
 
-// The s digit planes of an n x n FP64 matrix (transpose = 0: M = src by rows;
-// 1: M = src^T, i.e. by columns), with the exponent of M's row r from mx[r].
-// One workgroup per 64 x 64 region of M, staged in LDS as M[r][k]; each thread
-// then writes one 16-byte chunk of every plane.
 // Moduli of the residue form, as the slicing kernel takes them.
 struct CrtMods {
   int n;
@@ -111,7 +107,7 @@ struct CrtMods {
 // (r - m for r > 127: at least -128 for m = 256, -127 for odd m)
 __device__ __forceinline__ unsigned residue8(double x, double m, double inv) {
   const double q = floor(x * inv);
-  double r = fma(-q, m, x);                   // exact: |q m| < 2^54 and r is an integer
+  double r = fma(-q, m, x);                   // exact: an integer below 2 m in magnitude
   if (r < 0.0) r += m;
   else if (r >= m) r -= m;
   int ri = (int)r;
@@ -119,6 +115,11 @@ __device__ __forceinline__ unsigned residue8(double x, double m, double inv) {
   return (unsigned)ri & 0xffu;
 }
 
+// The s digit planes of an n x n FP64 matrix (transpose = 0: M = src by rows;
+// 1: M = src^T, i.e. by columns), with the exponent of M's row r from mx[r];
+// with CRT, the cm.n residue planes of its rows scaled to integers instead.
+// One workgroup per 64 x 64 region of M, staged in LDS as M[r][k]; each thread
+// then writes one 16-byte chunk of every plane.
 template <bool CRT>
 __global__ __launch_bounds__(256) void slices_kernel(const double* __restrict__ src, int n,
                                                      int transpose, const u64* __restrict__ mx,
