@@ -117,6 +117,24 @@ def test_workspace_bytes(ns):
         ns.ns_workspace_bytes(0, "radix9", "f64")
 
 
+def test_workspace_bytes_of_the_emulated_residuals(ns):
+    """The emulated residual adds its planes to the workspace: s digit planes
+    per operand and an FP64 partial-sum matrix for the digit form, one plane
+    per modulus for each operand and for the reduced products in the residue
+    form (ns.h: 14 moduli at n = 8192, 13 at n = 256)."""
+    base = ns.ns_workspace_bytes(8192, "radix9_resid", "split_bf16")
+    mat = 8192 * 8192
+    i8 = ns.ns_workspace_bytes(8192, "radix9_resid", "split_bf16+i8") - base
+    crt = ns.ns_workspace_bytes(8192, "radix9_resid", "split_bf16+crt") - base
+    assert 2 * 7 * mat + 8 * mat <= i8 < 2 * 7 * mat + 8 * mat + 2 ** 20
+    assert 3 * 14 * mat <= crt < 3 * 14 * mat + 2 ** 20
+    small = ns.ns_workspace_bytes(200, "hensel", "f32_acc64+crt") - \
+        ns.ns_workspace_bytes(200, "hensel", "f32_acc64")
+    assert 3 * 13 * 256 * 256 <= small < 3 * 13 * 256 * 256 + 2 ** 20
+    with pytest.raises(ns.NSError):                       # unknown modifier bits
+        ns.ns_workspace_bytes(256, "radix9_resid", ns.SPLIT_BF16 | 0x800)
+
+
 def test_status_strings(ns):
     assert ns.ns_status_string(0) == "ok"
     assert "argument" in ns.ns_status_string(-1)
